@@ -1,0 +1,194 @@
+"""Oracle -- TEST INFRASTRUCTURE ONLY.
+
+Python wrapper over the plain C oracle in ``orc.c`` (and the learned-proposal
+oracle in ``mlp.py``).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library under ``paper_1004_0024_amd/``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = [os.path.join(HERE, "orc.c")]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, no hand-written SIMD)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-march=native", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
+               "-Wall", "-Wextra", "-o", tmp] + SOURCES + ["-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("ORACLE_LIB", LIB_PATH)  # a mutated build, for the pin audit
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
+            build(force=False)
+        L = C.CDLL(path)
+        P = C.c_void_p
+        i32, i64, u32 = C.c_int32, C.c_int64, C.c_uint32
+        L.orc_mt_stream.argtypes = [u32, i64, i64, P]
+        L.orc_new.argtypes = [i32, i32, P, P, P, P, i32, P, P, u32]
+        L.orc_new.restype = P
+        L.orc_free.argtypes = [P]
+        L.orc_sweeps.argtypes = [P, i32, i32, P, P, P]
+        L.orc_swap_round.argtypes = [P, i32]
+        L.orc_run_many.argtypes = [i32, P, i32, i32, i32]
+        for name in ("orc_N", "orc_K"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = i32
+        for name in ("orc_sweeps_done", "orc_rounds_done", "orc_check_fields"):
+            getattr(L, name).argtypes = [P]
+            getattr(L, name).restype = i64
+        L.orc_energy_of.argtypes = [P, i32]
+        L.orc_energy_of.restype = i64
+        for name in ("orc_get_spins", "orc_get_fields", "orc_get_energy"):
+            getattr(L, name).argtypes = [P, P]
+        L.orc_get_labels.argtypes = [P, P, P]
+        L.orc_get_mt.argtypes = [P, P, P]
+        L.orc_get_swap_mt.argtypes = [P, P, P]
+        L.orc_get_counters.argtypes = [P, P, P, P, P]
+        L.orc_set_spins.argtypes = [P, i32, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def mt_stream(seed: int, n: int, skip: int = 0) -> np.ndarray:
+    out = np.empty(n, np.uint32)
+    lib().orc_mt_stream(seed, skip, n, _ptr(out))
+    return out
+
+
+class Chain:
+    """One system under the oracle: K walkers + one swap stream."""
+
+    def __init__(self, N, u, v, J, h, beta, walker_seeds, swap_seed):
+        self._keep = [np.ascontiguousarray(u, np.int32), np.ascontiguousarray(v, np.int32),
+                      np.ascontiguousarray(J, np.int8), np.ascontiguousarray(h, np.int8),
+                      np.ascontiguousarray(beta, np.float64), np.ascontiguousarray(walker_seeds, np.uint32)]
+        u_, v_, J_, h_, b_, ws_ = self._keep
+        assert len(ws_) == len(b_) and len(h_) == N
+        self.N, self.K = int(N), int(len(b_))
+        self.h = self._keep[3]
+        self._c = lib().orc_new(self.N, len(u_), _ptr(u_), _ptr(v_), _ptr(J_), _ptr(h_), self.K,
+                                _ptr(b_), _ptr(ws_), int(swap_seed))
+        if not self._c:
+            raise ValueError("oracle rejected the system")
+
+    @classmethod
+    def from_system(cls, system, walker_seeds, swap_seed):
+        N, u, v, J, h = system.expand()
+        return cls(N, u, v, J, h, system.beta, walker_seeds, swap_seed)
+
+    def __del__(self):
+        c = getattr(self, "_c", None)
+        if c:
+            lib().orc_free(c)
+            self._c = None
+
+    def sweeps(self, n, swap_every=1, record_energy=False, record_bits=False, record_spins=False):
+        K, N = self.K, self.N
+        e = np.zeros((n, K), np.int32) if record_energy else None
+        b = np.zeros((n, K), np.uint32) if record_bits else None
+        ss = np.zeros((K, N), np.int64) if record_spins else None
+        lib().orc_sweeps(self._c, n, swap_every,
+                         _ptr(e) if e is not None else None,
+                         _ptr(b) if b is not None else None,
+                         _ptr(ss) if ss is not None else None)
+        return {"energy": e, "bits": b, "slot_spin_sum": ss}
+
+    def swap_round(self, parity):
+        lib().orc_swap_round(self._c, parity)
+
+    def spins(self):
+        out = np.empty((self.K, self.N), np.int8)
+        lib().orc_get_spins(self._c, _ptr(out))
+        return out
+
+    def fields(self):
+        out = np.empty((self.K, self.N), np.int32)
+        lib().orc_get_fields(self._c, _ptr(out))
+        return out
+
+    def energy(self):
+        out = np.empty(self.K, np.int64)
+        lib().orc_get_energy(self._c, _ptr(out))
+        return out
+
+    def labels(self):
+        t = np.empty(self.K, np.int32)
+        w = np.empty(self.K, np.int32)
+        lib().orc_get_labels(self._c, _ptr(t), _ptr(w))
+        return t, w
+
+    def mt(self):
+        win = np.empty((self.K, 624), np.uint32)
+        used = np.empty(self.K, np.int64)
+        lib().orc_get_mt(self._c, _ptr(win), _ptr(used))
+        return win, used
+
+    def swap_mt(self):
+        win = np.empty(624, np.uint32)
+        used = np.zeros(1, np.int64)
+        lib().orc_get_swap_mt(self._c, _ptr(win), _ptr(used))
+        return win, int(used[0])
+
+    def counters(self):
+        f = np.empty(self.K, np.uint64)
+        a = np.empty(self.K, np.uint64)
+        c = np.empty(self.K, np.uint64)
+        n = np.zeros(1, np.uint64)
+        lib().orc_get_counters(self._c, _ptr(f), _ptr(a), _ptr(c), _ptr(n))
+        return {"flips": f, "swap_att": a, "swap_acc": c, "near": int(n[0])}
+
+    def energy_of(self, w):
+        return int(lib().orc_energy_of(self._c, w))
+
+    def check_fields(self):
+        return int(lib().orc_check_fields(self._c))
+
+    def set_spins(self, w, s):
+        s = np.ascontiguousarray(s, np.int8)
+        lib().orc_set_spins(self._c, w, _ptr(s))
+
+    @property
+    def sweeps_done(self):
+        return int(lib().orc_sweeps_done(self._c))
+
+    @property
+    def rounds_done(self):
+        return int(lib().orc_rounds_done(self._c))
+
+
+def run_many(chains, n, swap_every, n_threads):
+    arr = (C.c_void_p * len(chains))(*[c._c for c in chains])
+    lib().orc_run_many(len(chains), arr, n, swap_every, n_threads)
+
+
+def workload_chains(workload, idx=None):
+    """Oracle chains for systems `idx` of a workload, with the workload's seeds."""
+    idx = range(len(workload.systems)) if idx is None else idx
+    out = []
+    for s in idx:
+        b0, b1 = workload.walker_base[s], workload.walker_base[s + 1]
+        out.append(Chain.from_system(workload.systems[s], workload.walker_seeds[b0:b1],
+                                     int(workload.swap_seeds[s])))
+    return out

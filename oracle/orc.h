@@ -1,0 +1,84 @@
+/*
+ * Oracle for the parallel-tempering Metropolis path -- TEST INFRASTRUCTURE.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the GPU library
+ * computes.  Only the tests, the smoke check and the benchmark's CPU baseline
+ * may load it; the product path never does.  It shares no code, header, table
+ * or constant generator with the HIP library.
+ *
+ * Method (Dickson, Karimi & Hamze, "Importance of Explicit Vectorization for
+ * CPU and GPU Software Performance", 2010):
+ *   - Ising cost f(s) = -sum_i h_i s_i - sum_{edges} J_ij s_i s_j   (Sec. 1)
+ *   - Metropolis sweep in ascending spin order, one uniform per spin, flip
+ *     when it falls below the flip probability, then update the local data of
+ *     the neighbours (Fig. 1; neighbour update as in Figs. 3 and 6)
+ *   - MT19937 random numbers (Sec. 3, Fig. 8)
+ *   - parallel tempering over a ladder of inverse temperatures (Sec. 1)
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* MT19937 with a circular window of the last 624 generated words. */
+typedef struct orc_mt {
+  uint32_t x[624];
+  int64_t n; /* outputs delivered so far */
+} orc_mt;
+
+void orc_mt_seed(orc_mt *g, uint32_t seed);
+uint32_t orc_mt_next(orc_mt *g);
+/* x_{n} .. x_{n+623}: the 624 most recent words, oldest first. */
+void orc_mt_window(const orc_mt *g, uint32_t *out624);
+/* outputs [skip, skip+n) of the stream seeded with `seed`. */
+void orc_mt_stream(uint32_t seed, int64_t skip, int64_t n, uint32_t *out);
+
+typedef struct orc_chain orc_chain;
+
+/* One system: N spins, nE undirected edges (u[e], v[e], J[e]), fields h[N];
+ * K walkers, walker w starts at temperature slot w; walker w's stream is
+ * seeded walker_seed[w], the swap stream swap_seed.  Returns NULL on bad input. */
+orc_chain *orc_new(int32_t N, int32_t nE, const int32_t *u, const int32_t *v, const int8_t *J,
+                   const int8_t *h, int32_t K, const double *beta, const uint32_t *walker_seed,
+                   uint32_t swap_seed);
+void orc_free(orc_chain *c);
+
+/* n sweeps; after every sweep whose running count is a multiple of
+ * swap_every (>0) one round of neighbour swaps, parity = rounds done mod 2.
+ * Optional records after each sweep (and its swap round), per slot k:
+ *   e_series[t*K + k]      energy of the walker at slot k
+ *   bits_series[t*K + k]   its spins as bits (bit i = s_i == +1), N <= 32
+ *   slot_spin_sum[k*N + i] += s_i of the walker at slot k                     */
+void orc_sweeps(orc_chain *c, int32_t n, int32_t swap_every, int32_t *e_series,
+                uint32_t *bits_series, int64_t *slot_spin_sum);
+void orc_swap_round(orc_chain *c, int32_t parity);
+/* The same n sweeps on many independent chains, spread over threads. */
+void orc_run_many(int32_t n_chains, orc_chain **chains, int32_t n, int32_t swap_every,
+                  int32_t n_threads);
+
+int32_t orc_N(const orc_chain *c);
+int32_t orc_K(const orc_chain *c);
+int64_t orc_sweeps_done(const orc_chain *c);
+int64_t orc_rounds_done(const orc_chain *c);
+void orc_get_spins(const orc_chain *c, int8_t *out);   /* [K][N] +-1 */
+void orc_get_fields(const orc_chain *c, int32_t *out); /* [K][N] h_eff */
+void orc_get_energy(const orc_chain *c, int64_t *out); /* [K] running energy */
+void orc_get_labels(const orc_chain *c, int32_t *temp_of, int32_t *walker_at);
+void orc_get_mt(const orc_chain *c, uint32_t *win /*[K][624]*/, int64_t *used /*[K]*/);
+void orc_get_swap_mt(const orc_chain *c, uint32_t *win624, int64_t *used);
+void orc_get_counters(const orc_chain *c, uint64_t *flips /*[K]*/, uint64_t *sw_att /*[K]*/,
+                      uint64_t *sw_acc /*[K]*/, uint64_t *near_threshold);
+/* Energy of walker w's spins by the cost function itself. */
+int64_t orc_energy_of(const orc_chain *c, int32_t w);
+/* Number of running fields / energies that differ from a recomputation. */
+int64_t orc_check_fields(const orc_chain *c);
+/* Overwrite a walker's spins (fields and energy are recomputed). */
+void orc_set_spins(orc_chain *c, int32_t w, const int8_t *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -27,14 +27,28 @@ stream is seeded ``5489 + R_total + s``.
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+from functools import lru_cache
 
 import numpy as np
 
 VALUES = np.array([-3, -2, -1, 1, 2, 3], dtype=np.int8)
 
 
+@lru_cache(maxsize=None)
+def _chimera_template_cached(L: int):
+    S, u, v = _chimera_template(L)
+    u.setflags(write=False)
+    v.setflags(write=False)
+    return S, u, v
+
+
 def chimera_template(L: int):
     """In-slice edges of an L x L grid of K4,4 cells: (S, u, v) with u < v."""
+    S, u, v = _chimera_template_cached(L)
+    return S, u.copy(), v.copy()
+
+
+def _chimera_template(L: int):
     if L < 1:
         raise ValueError("L must be >= 1")
     us, vs = [], []

@@ -1,0 +1,184 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) parallel-tempering Metropolis library.
+ *
+ * The operation is the Metropolis sweep of Dickson, Karimi & Hamze, "Importance
+ * of Explicit Vectorization for CPU and GPU Software Performance" (2010):
+ *   - Ising cost f(s) = -sum_i h_i s_i - sum_{i<j} J_ij s_i s_j, s_i = +-1
+ *     (Section 1, equation of f; each undirected edge counted once, so
+ *     J > 0 favours aligned spins);
+ *   - one sweep visits every spin in ascending index order, draws one uniform
+ *     number per spin and flips the spin when the number is below the flip
+ *     probability min(1, exp(-beta * dE)), dE = 2 s_i h_eff_i, then updates
+ *     what its neighbours need (Figure 1; neighbour data as in Figures 3, 6);
+ *   - the uniform numbers come from MT19937 (Section 3, Figure 8), one stream
+ *     per walker;
+ *   - many walkers run at once under parallel tempering (Section 1): after a
+ *     sweep, walkers at neighbouring inverse temperatures exchange their
+ *     temperature labels with probability min(1, exp((b_k - b_k+1)(E_k - E_k+1))).
+ *   - the systems are layered: many identical copies ("slices") of a small
+ *     Ising model, corresponding spins of adjacent slices joined, the last
+ *     slice optionally wrapping to the first (Section 3.1); every spin has at
+ *     most 8 neighbours (Section 1).
+ *
+ * Conventions
+ *   - Spin (m, q) of a system with S spins per slice and M slices has index
+ *     i = m*S + q; the sweep order is ascending i.
+ *   - Walker r (global, over all systems in load order) uses uniform
+ *     u_n * 2^-32 where u_n is the n-th MT19937 output of its stream; its
+ *     initial spin i is +1 iff the top bit of output i is set, so sweep t
+ *     (0-based) uses outputs (t+1)*N .. (t+2)*N - 1.
+ *   - A flip of spin i with d = s_i * h_eff_i is accepted iff d <= 0 or
+ *     u < ceil(2^32 * exp(-2.0 * beta * d)) (IEEE double, beta the walker's
+ *     current inverse temperature); the integer threshold is exactly the
+ *     comparison u * 2^-32 < exp(-2.0 * beta * d).
+ *   - Swap rounds are deterministic even/odd: round number n tries the pairs
+ *     (k, k+1) with k = n mod 2, 4, ... in ascending k, one draw of the
+ *     system's swap stream per pair, accepted iff delta >= 0 or
+ *     u * 2^-32 < exp(delta), delta = (beta_k - beta_k+1) * (E_a - E_b) in
+ *     IEEE double, a / b the walkers at slots k / k+1.  Decisions with
+ *     |u * 2^-32 - exp(delta)| < 1e-12 are counted (stats[ISING_STAT_NEAR]).
+ *
+ * Ownership: every device buffer belongs to the caller (e.g. torch tensors);
+ * the library never allocates device memory.  Host arrays passed in are read
+ * during the call only.  All calls are asynchronous on `stream` (a
+ * hipStream_t, NULL for the default stream) unless stated; device-side
+ * failures surface as ISING_E_HIP from a later call.  One stream per graph,
+ * no internal locking.  Return codes below; no call aborts the process.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ISING_OK = 0,
+  ISING_E_INVAL = -1, /* null pointer, negative count, inconsistent description */
+  ISING_E_RANGE = -2, /* outside the supported envelope (sizes, degree, field bound) */
+  ISING_E_SIZE = -3,  /* a caller buffer is too small */
+  ISING_E_HIP = -4,   /* HIP runtime error; see ising_last_error() */
+  ISING_E_STATE = -5  /* call out of order (e.g. a sweep before ising_init_state) */
+};
+
+/* Supported envelope. */
+#define ISING_MAX_S 512     /* spins per slice (threads per walker) */
+#define ISING_MAX_DEG 8     /* in-slice neighbours per spin (tau edges extra, total <= 8) */
+#define ISING_MAX_D 63      /* |h_i| + sum_j |J_ij| */
+#define ISING_MAX_K 256     /* walkers (= temperature slots) per system */
+#define ISING_MT_WORDS 624  /* MT19937 state words */
+
+/* One system (host memory, read during ising_graph_bytes / ising_load_graph).
+ * Layered form: an S-spin template with `n_edges` in-slice edges, copied into
+ * M slices; spin (m, q) is joined to (m+1, q) with coupling J_tau[q] for
+ * m = 0 .. M-2, and for a ring (M >= 3) also (M-1, q) to (0, q).
+ * M = 1 describes an arbitrary graph on S spins (J_tau ignored).            */
+typedef struct {
+  int32_t spins_per_slice; /* S, 1 .. ISING_MAX_S */
+  int32_t n_slices;        /* M >= 1 */
+  int32_t ring;            /* 0 or 1 (1 needs M >= 3) */
+  int32_t n_edges;         /* in-slice template edges */
+  const int32_t *edge_u;   /* [n_edges], 0 <= u, v < S, u != v, no duplicates */
+  const int32_t *edge_v;
+  const int8_t *edge_J;    /* [n_edges] */
+  const int8_t *h;         /* [S] */
+  const int8_t *J_tau;     /* [S]; may be NULL when M == 1 */
+  int32_t n_temps;         /* K >= 1: walkers of this system = temperature slots */
+  const double *beta;      /* [K] inverse temperatures of the slots, > 0 */
+} ising_system_desc;
+
+typedef struct ising_graph ising_graph; /* opaque; owns host metadata only */
+
+/* Bytes of device memory the packed tables of these systems need. */
+int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys, size_t *dev_bytes);
+
+/* Validate and pack the systems (neighbour rows with J inline, Section 2.2,
+ * Figures 5-6; integer thresholds per slot, Section 2.3 result caching), copy
+ * the tables into the caller's device buffer `dev_tables` (>= the size from
+ * ising_graph_bytes, 256-byte aligned, kept alive while the graph is used)
+ * and return a handle.  Synchronous with respect to the host arrays.         */
+int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys, void *dev_tables,
+                         size_t bytes, void *stream, ising_graph **out);
+void ising_free_graph(ising_graph *g);
+
+/* Totals of a loaded graph, written to out[0..n-1] in this order:
+ *   0 n_sys, 1 walkers R, 2 slots (sum K), 3 spin words (uint32) of all walkers,
+ *   4 sum over walkers of N (attempts per sweep), 5 max levels per sweep.   */
+int32_t ising_graph_info(const ising_graph *g, int64_t *out, int32_t n);
+/* Per walker r: first uint32 word of its bit-packed spins; per system s its
+ * slice row length in words (row_words[s]).  Bit q of word
+ * spin_word[r] + m*row_words[s] + (q >> 5) ... is bit (q & 31): spin (m, q)
+ * of walker r is +1 iff that bit is set.  Host arrays [R] and [n_sys].      */
+int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row_words);
+
+/* Device buffers of the chain (caller-owned).  Element counts come from
+ * ising_state_sizes; walker r of system s is walker r - first(s) there.    */
+typedef struct {
+  uint32_t *spins;     /* bit-packed spins, layout per ising_spin_layout */
+  uint32_t *mt;        /* [R][624]: walker r's 624 most recent MT words, oldest first */
+  int32_t *energy;     /* [R] running cost f(s) */
+  int32_t *temp_of;    /* [R] temperature slot (0..K-1 within its system) */
+  int32_t *walker_at;  /* [slots] walker (index within its system) at each slot */
+  uint32_t *swap_mt;   /* [n_sys][624] swap streams, same window convention */
+  uint64_t *flips;     /* [R] accepted flips */
+  uint64_t *swap_att;  /* [slots] attempts of pair (k, k+1), at slot index k */
+  uint64_t *swap_acc;  /* [slots] acceptances */
+  uint64_t *stats;     /* [ISING_N_STATS] */
+  int64_t sweeps;      /* host: sweeps done (set by the library) */
+  int64_t rounds;      /* host: swap rounds done */
+} ising_state;
+
+enum {
+  ISING_STAT_NEAR = 0,       /* swap decisions within 1e-12 of the threshold */
+  ISING_STAT_WAVE_STEPS = 1, /* (wavefront, level) steps with an active spin */
+  ISING_STAT_WAVE_FLIP = 2,  /* of those, steps in which some lane flipped */
+  ISING_STAT_ATTEMPTS = 3,   /* spin-flip attempts */
+  ISING_N_STATS = 8
+};
+
+/* Element counts: [spins, mt, energy, temp_of, walker_at, swap_mt, flips,
+ * swap_att, swap_acc, stats]. */
+#define ISING_STATE_NARRAYS 10
+int32_t ising_state_sizes(const ising_graph *g, int64_t *counts);
+
+/* Seed every walker stream (MT19937 init_genrand with walker_seeds[r]) and
+ * swap stream (swap_seeds[s]), draw the initial spins, compute energies,
+ * put walker j of each system at slot j, clear the counters.  Host arrays. */
+int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *walker_seeds,
+                         const uint32_t *swap_seeds, void *stream);
+
+/* n_sweeps sweeps of every walker; after each sweep whose running count is a
+ * multiple of swap_every (> 0; 0 = never) one swap round of every system.
+ * e_series (device, nullable): [n_sweeps][slots] energy of the walker at each
+ * slot after each sweep and its swap round.                                  */
+int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,
+                    int32_t *e_series, void *stream);
+
+/* One swap round of every system with the given parity (0: pairs (0,1),(2,3)..;
+ * 1: (1,2),(3,4)..).  Does not change st->rounds.                             */
+int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream);
+
+/* Observables per walker into device int32 obs[R][4]: cost recomputed from the
+ * spins, magnetisation sum_i s_i, running cost, temperature slot.            */
+int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *obs, void *stream);
+
+/* ---- host-only helpers (no device work; usable without a GPU) ------------ */
+
+/* thr[d] = ceil(2^32 * exp(-2.0 * beta * d)) - 1 for d = 1..dmax, thr[0] =
+ * 0xffffffff: a flip with d <= 0 or u <= thr[d] is accepted.                */
+int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr);
+/* Level offsets of the exact parallel schedule of one template: f[q] is the
+ * length of the longest chain of in-slice edges leading to q in ascending
+ * index order; *depth = max f + 1.                                           */
+int32_t ising_level_offsets(const ising_system_desc *sys, int32_t *f, int32_t *depth);
+
+/* Last error message of this thread ("" if none). */
+const char *ising_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISING_H */

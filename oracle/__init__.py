@@ -22,7 +22,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no hand-written SIMD)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-march=native", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
                "-Wall", "-Wextra", "-o", tmp] + SOURCES + ["-lm", "-lpthread"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)

@@ -1,0 +1,237 @@
+"""ctypes binding of the C ABI (include/ising.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_FILE = os.path.join(HERE, "libising.so")
+
+ISING_N_STATS = 8
+STAT_NEAR, STAT_WAVE_STEPS, STAT_WAVE_FLIP, STAT_ATTEMPTS = 0, 1, 2, 3
+_ERRORS = {-1: "E_INVAL", -2: "E_RANGE", -3: "E_SIZE", -4: "E_HIP", -5: "E_STATE"}
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [
+        ("spins_per_slice", C.c_int32), ("n_slices", C.c_int32), ("ring", C.c_int32),
+        ("n_edges", C.c_int32), ("edge_u", C.c_void_p), ("edge_v", C.c_void_p),
+        ("edge_J", C.c_void_p), ("h", C.c_void_p), ("J_tau", C.c_void_p),
+        ("n_temps", C.c_int32), ("beta", C.c_void_p),
+    ]
+
+
+class StateStruct(C.Structure):
+    _fields_ = [
+        ("spins", C.c_void_p), ("mt", C.c_void_p), ("energy", C.c_void_p), ("temp_of", C.c_void_p),
+        ("walker_at", C.c_void_p), ("swap_mt", C.c_void_p), ("flips", C.c_void_p),
+        ("swap_att", C.c_void_p), ("swap_acc", C.c_void_p), ("stats", C.c_void_p),
+        ("sweeps", C.c_int64), ("rounds", C.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_FILE
+
+
+def lib():
+    """The loaded libising.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_FILE):
+            raise ImportError(f"{_LIB_FILE} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(_LIB_FILE)
+        P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "ising_graph_bytes": ([P, i32, P], i32),
+            "ising_load_graph": ([P, i32, P, sz, P, P], i32),
+            "ising_free_graph": ([P], None),
+            "ising_graph_info": ([P, P, i32], i32),
+            "ising_spin_layout": ([P, P, P], i32),
+            "ising_state_sizes": ([P, P], i32),
+            "ising_init_state": ([P, P, P, P, P], i32),
+            "ising_sweep": ([P, P, i32, i32, P, P], i32),
+            "pt_swap": ([P, P, i32, P], i32),
+            "ising_observables": ([P, P, P, P], i32),
+            "ising_threshold_row": ([C.c_double, i32, P], i32),
+            "ising_level_offsets": ([P, P, P], i32),
+            "ising_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise IsingError(rc, lib().ising_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _descs(systems):
+    """ising_system_desc array for objects with S, M, ring, eu, ev, eJ, h, J_tau, beta."""
+    keep, arr = [], (SystemDesc * len(systems))()
+    for i, s in enumerate(systems):
+        eu = np.ascontiguousarray(s.eu, np.int32)
+        ev = np.ascontiguousarray(s.ev, np.int32)
+        eJ = np.ascontiguousarray(s.eJ, np.int8)
+        h = np.ascontiguousarray(s.h, np.int8)
+        jt = np.ascontiguousarray(s.J_tau if s.J_tau is not None else np.zeros(s.S, np.int8), np.int8)
+        beta = np.ascontiguousarray(s.beta, np.float64)
+        keep += [eu, ev, eJ, h, jt, beta]
+        arr[i] = SystemDesc(int(s.S), int(s.M), int(bool(s.ring)), int(eu.shape[0]), _np_ptr(eu), _np_ptr(ev),
+                            _np_ptr(eJ), _np_ptr(h), _np_ptr(jt), int(beta.shape[0]), _np_ptr(beta))
+    return arr, keep
+
+
+def threshold_row(beta: float, dmax: int) -> np.ndarray:
+    out = np.zeros(dmax + 1, np.uint32)
+    _check(lib().ising_threshold_row(float(beta), int(dmax), _np_ptr(out)))
+    return out
+
+
+def level_offsets(system):
+    arr, keep = _descs([system])
+    f = np.zeros(int(system.S), np.int32)
+    depth = C.c_int32(0)
+    _check(lib().ising_level_offsets(C.byref(arr[0]), _np_ptr(f), C.byref(depth)))
+    return f, int(depth.value)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    """Loaded systems: device tables in a torch buffer + the library handle."""
+
+    def __init__(self, systems, device="cuda"):
+        import torch
+        self.systems = list(systems)
+        arr, keep = _descs(self.systems)
+        nbytes = C.c_size_t(0)
+        _check(lib().ising_graph_bytes(arr, len(self.systems), C.byref(nbytes)))
+        self.tables = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=device)
+        base = self.tables.data_ptr()
+        off = (-base) % 256
+        self._handle = C.c_void_p()
+        _check(lib().ising_load_graph(arr, len(self.systems), C.c_void_p(base + off), nbytes.value,
+                                      _stream(), C.byref(self._handle)))
+        info = np.zeros(6, np.int64)
+        _check(lib().ising_graph_info(self._handle, _np_ptr(info), 6))
+        self.n_sys, self.R, self.slots, self.spin_words, self.attempts_per_sweep, self.max_levels = \
+            (int(x) for x in info)
+        self.spin_word = np.zeros(self.R, np.int64)
+        self.row_words = np.zeros(self.n_sys, np.int32)
+        _check(lib().ising_spin_layout(self._handle, _np_ptr(self.spin_word), _np_ptr(self.row_words)))
+        Ks = np.array([len(s.beta) for s in self.systems], np.int64)
+        self.walker_base = np.concatenate([[0], np.cumsum(Ks)])
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h and _lib is not None:
+            _lib.ising_free_graph(h)
+            self._handle = None
+
+    @property
+    def handle(self):
+        return self._handle
+
+
+class State:
+    """Chain state in torch device tensors, walker-major."""
+
+    _FIELDS = ["spins", "mt", "energy", "temp_of", "walker_at", "swap_mt", "flips", "swap_att", "swap_acc",
+               "stats"]
+
+    def __init__(self, graph: Graph):
+        import torch
+        self.graph = graph
+        counts = np.zeros(10, np.int64)
+        _check(lib().ising_state_sizes(graph.handle, _np_ptr(counts)))
+        dev = graph.tables.device
+        dt = {"spins": torch.int32, "mt": torch.int32, "energy": torch.int32, "temp_of": torch.int32,
+              "walker_at": torch.int32, "swap_mt": torch.int32, "flips": torch.int64, "swap_att": torch.int64,
+              "swap_acc": torch.int64, "stats": torch.int64}
+        self.t = {}
+        for name, n in zip(self._FIELDS, counts):
+            self.t[name] = torch.zeros(max(int(n), 1), dtype=dt[name], device=dev)
+        self._s = StateStruct(*[C.c_void_p(self.t[n].data_ptr()) for n in self._FIELDS], 0, -1)
+
+    @property
+    def sweeps(self):
+        return int(self._s.sweeps)
+
+    @property
+    def rounds(self):
+        return int(self._s.rounds)
+
+    def init(self, walker_seeds, swap_seeds):
+        ws = np.ascontiguousarray(walker_seeds, np.uint32)
+        ss = np.ascontiguousarray(swap_seeds, np.uint32)
+        assert ws.shape[0] == self.graph.R and ss.shape[0] == self.graph.n_sys
+        _check(lib().ising_init_state(self.graph.handle, C.byref(self._s), _np_ptr(ws), _np_ptr(ss), _stream()))
+        return self
+
+    def sweep(self, n_sweeps, swap_every=1, record=False):
+        import torch
+        e = None
+        if record:
+            e = torch.zeros((n_sweeps, self.graph.slots), dtype=torch.int32, device=self.graph.tables.device)
+        _check(lib().ising_sweep(self.graph.handle, C.byref(self._s), int(n_sweeps), int(swap_every),
+                                 C.c_void_p(e.data_ptr()) if e is not None else None, _stream()))
+        return e
+
+    def swap(self, parity):
+        _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))
+
+    def observables(self):
+        import torch
+        obs = torch.zeros((self.graph.R, 4), dtype=torch.int32, device=self.graph.tables.device)
+        _check(lib().ising_observables(self.graph.handle, C.byref(self._s), C.c_void_p(obs.data_ptr()), _stream()))
+        return obs
+
+    # ---- host views of the device state (for tests and reports) ----
+    def host(self, name):
+        return self.t[name].cpu().numpy()
+
+    def spins_pm(self, systems=None):
+        """Spins as +-1 int8 arrays, one [K, N] array per requested system."""
+        g = self.graph
+        words = self.host("spins").view(np.uint32)
+        out = []
+        for s in (range(g.n_sys) if systems is None else systems):
+            sysm = g.systems[s]
+            S, M, K = int(sysm.S), int(sysm.M), len(sysm.beta)
+            SW = int(g.row_words[s])
+            w0 = int(g.walker_base[s])
+            base = g.spin_word[w0]
+            blk = words[base: base + K * M * SW].reshape(K, M, SW)
+            bits = np.unpackbits(blk.view(np.uint8).reshape(K, M, SW * 4), axis=2, bitorder="little")[:, :, :S]
+            out.append((bits.astype(np.int8) * 2 - 1).reshape(K, S * M))
+        return out
+
+    def mt_window(self):
+        return self.host("mt").view(np.uint32).reshape(self.graph.R, 624)
+
+    def swap_window(self):
+        return self.host("swap_mt").view(np.uint32).reshape(self.graph.n_sys, 624)

@@ -1,0 +1,476 @@
+// Host side of the C ABI declared in include/ising.h: validation, packing of
+// the layered systems into device tables, tiling, launch sequencing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "internal.h"
+
+using namespace ising;
+
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static int32_t hip_fail(hipError_t e, const char *where) {
+  return fail(ISING_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                     \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+extern "C" const char *ising_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Host-only helpers
+// ---------------------------------------------------------------------------
+extern "C" int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr) {
+  if (!thr || dmax < 0 || dmax > 1023) return fail(ISING_E_INVAL, "threshold_row: bad arguments");
+  if (!(beta > 0.0) || !isfinite(beta)) return fail(ISING_E_RANGE, "threshold_row: beta must be > 0");
+  thr[0] = 0xffffffffu;
+  for (int32_t d = 1; d <= dmax; ++d) {
+    // u * 2^-32 < p  <=>  u < ceil(2^32 p)  <=>  u <= ceil(2^32 p) - 1 for integer u.
+    const double p = exp(-2.0 * beta * (double)d);
+    const double t = ceil(ldexp(p, 32));  // exact: scaling by 2^32, ceil of a double
+    const uint64_t ti = (uint64_t)t;      // 1 .. 2^32
+    thr[d] = (uint32_t)(ti - 1u);
+  }
+  return ISING_OK;
+}
+
+struct SysHost {
+  int32_t S, M, ring, F, deg, dmax, K;
+  std::vector<TmplSpin> tmpl;
+  std::vector<double> beta;
+};
+
+static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &out) {
+  const int32_t S = d.spins_per_slice, M = d.n_slices;
+  if (S < 1 || S > ISING_MAX_S) return fail(ISING_E_RANGE, "system %d: S=%d outside 1..%d", idx, S, ISING_MAX_S);
+  if (M < 1) return fail(ISING_E_INVAL, "system %d: n_slices must be >= 1", idx);
+  if ((int64_t)S * M > (1 << 22)) return fail(ISING_E_RANGE, "system %d: too many spins", idx);
+  if (d.ring != 0 && d.ring != 1) return fail(ISING_E_INVAL, "system %d: ring must be 0 or 1", idx);
+  if (d.ring && M < 3) return fail(ISING_E_RANGE, "system %d: a ring needs M >= 3", idx);
+  if (d.n_edges < 0 || (d.n_edges > 0 && (!d.edge_u || !d.edge_v || !d.edge_J)))
+    return fail(ISING_E_INVAL, "system %d: edge arrays", idx);
+  if (!d.h) return fail(ISING_E_INVAL, "system %d: h is NULL", idx);
+  if (M > 1 && !d.J_tau) return fail(ISING_E_INVAL, "system %d: J_tau is NULL with M > 1", idx);
+  if (d.n_temps < 1 || d.n_temps > ISING_MAX_K)
+    return fail(ISING_E_RANGE, "system %d: K=%d outside 1..%d", idx, d.n_temps, ISING_MAX_K);
+  if (!d.beta) return fail(ISING_E_INVAL, "system %d: beta is NULL", idx);
+  for (int32_t k = 0; k < d.n_temps; ++k)
+    if (!(d.beta[k] > 0.0) || !isfinite(d.beta[k])) return fail(ISING_E_RANGE, "system %d: beta[%d] must be > 0", idx, k);
+
+  std::vector<std::vector<std::pair<int32_t, int8_t>>> nb(S);
+  std::set<std::pair<int32_t, int32_t>> seen;
+  for (int32_t e = 0; e < d.n_edges; ++e) {
+    int32_t a = d.edge_u[e], b = d.edge_v[e];
+    if (a < 0 || a >= S || b < 0 || b >= S || a == b)
+      return fail(ISING_E_INVAL, "system %d: edge %d (%d,%d) invalid", idx, e, a, b);
+    if (!seen.insert({std::min(a, b), std::max(a, b)}).second)
+      return fail(ISING_E_INVAL, "system %d: duplicate edge (%d,%d)", idx, a, b);
+    nb[a].push_back({b, d.edge_J[e]});
+    nb[b].push_back({a, d.edge_J[e]});
+  }
+  const int32_t ntau = M == 1 ? 0 : 2;  // worst case per spin (middle slices / ring)
+  out.S = S;
+  out.M = M;
+  out.ring = d.ring;
+  out.K = d.n_temps;
+  out.deg = 0;
+  out.dmax = 0;
+  out.tmpl.assign(S, TmplSpin{});
+  std::vector<int32_t> f(S, 0);
+  int32_t F = 1;
+  for (int32_t q = 0; q < S; ++q) {
+    if ((int32_t)nb[q].size() > ISING_MAX_DEG || (int32_t)nb[q].size() + ntau > 8)
+      return fail(ISING_E_RANGE, "system %d: spin %d has %d in-slice + %d tau neighbours (max 8)", idx, q,
+                  (int)nb[q].size(), ntau);
+    std::sort(nb[q].begin(), nb[q].end());
+    int32_t fq = 0, bound = std::abs((int32_t)d.h[q]);
+    for (auto &p : nb[q]) {
+      if (p.first < q) fq = std::max(fq, f[p.first] + 1);
+      bound += std::abs((int32_t)p.second);
+    }
+    const int32_t jt = M > 1 ? d.J_tau[q] : 0;
+    bound += ntau * std::abs(jt);
+    if (bound > ISING_MAX_D)
+      return fail(ISING_E_RANGE, "system %d: |h|+sum|J| = %d at spin %d exceeds %d", idx, bound, q, ISING_MAX_D);
+    f[q] = fq;
+    F = std::max(F, fq + 1);
+    out.dmax = std::max(out.dmax, bound);
+    out.deg = std::max(out.deg, (int32_t)nb[q].size());
+    TmplSpin &t = out.tmpl[q];
+    for (int j = 0; j < kMaxDeg; ++j) {
+      t.nbr[j] = (int16_t)q;
+      t.J[j] = 0;
+    }
+    for (size_t j = 0; j < nb[q].size(); ++j) {
+      t.nbr[j] = (int16_t)nb[q][j].first;
+      t.J[j] = nb[q][j].second;
+    }
+    t.h = d.h[q];
+    t.Jtau = (int8_t)jt;
+    t.f = (uint8_t)fq;
+    t.deg = (uint8_t)nb[q].size();
+  }
+  if (F > 255) return fail(ISING_E_RANGE, "system %d: schedule depth %d exceeds 255", idx, F);
+  out.F = F;
+  out.beta.assign(d.beta, d.beta + d.n_temps);
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_level_offsets(const ising_system_desc *sys, int32_t *f, int32_t *depth) {
+  if (!sys || !f || !depth) return fail(ISING_E_INVAL, "level_offsets: NULL argument");
+  SysHost h;
+  int32_t rc = build_system(*sys, 0, h);
+  if (rc) return rc;
+  for (int32_t q = 0; q < h.S; ++q) f[q] = h.tmpl[q].f;
+  *depth = h.F;
+  return ISING_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph handle
+// ---------------------------------------------------------------------------
+struct ising_graph {
+  int32_t n_sys = 0;
+  int64_t R = 0, slots = 0, spin_words = 0, attempts = 0, max_levels = 0;
+  std::vector<SysInfo> sys;
+  std::vector<Tile> tiles;
+  std::vector<Bucket> buckets;
+  std::vector<int32_t> walker_sys;
+  DevTables dev{};
+  size_t bytes = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t sys, tmpl, thr, beta, tiles, wsys, total;
+};
+
+static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R) {
+  Layout L{};
+  size_t o = 0;
+  L.sys = o;
+  o = align256(o + sizeof(SysInfo) * n_sys);
+  L.tmpl = o;
+  o = align256(o + sizeof(TmplSpin) * n_tmpl);
+  L.thr = o;
+  o = align256(o + sizeof(uint32_t) * kThrRow * slots);
+  L.beta = o;
+  o = align256(o + sizeof(double) * slots);
+  L.tiles = o;
+  o = align256(o + sizeof(Tile) * n_tiles);
+  L.wsys = o;
+  o = align256(o + sizeof(int32_t) * R);
+  L.total = o;
+  return L;
+}
+
+// Walkers per workgroup for a template of S spins: aim at ~512 threads and a
+// per-workgroup LDS budget that leaves room for two workgroups per CU.
+static int32_t choose_G(int32_t S, int32_t Kmax, int32_t ldsw_per_walker) {
+  int32_t G = std::max(1, 512 / S);
+  G = std::min(G, std::max(1, 1024 / S));
+  G = std::min(G, Kmax);
+  while (G > 1 && (size_t)G * ldsw_per_walker * 4 > 80 * 1024) --G;
+  return G;
+}
+
+static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
+  g.n_sys = (int32_t)hs.size();
+  g.sys.resize(hs.size());
+  int64_t walker = 0, slot = 0, word = 0, tmpl = 0;
+  for (size_t s = 0; s < hs.size(); ++s) {
+    const SysHost &h = hs[s];
+    SysInfo &si = g.sys[s];
+    si.S = h.S;
+    si.M = h.M;
+    si.ring = h.ring;
+    si.F = h.F;
+    si.SW = (h.S + 31) / 32;
+    si.WW = si.SW * h.M;
+    si.K = h.K;
+    si.walker0 = (int32_t)walker;
+    si.spin_word0 = word;
+    si.tmpl0 = (int32_t)tmpl;
+    si.thr0 = (int32_t)slot;
+    si.slot0 = (int32_t)slot;
+    si.deg = h.deg;
+    walker += h.K;
+    slot += h.K;
+    word += (int64_t)si.WW * h.K;
+    tmpl += h.S;
+    g.attempts += (int64_t)h.S * h.M * h.K;
+    g.max_levels = std::max<int64_t>(g.max_levels, h.M + h.F - 1);
+    for (int32_t k = 0; k < h.K; ++k) g.walker_sys.push_back((int32_t)s);
+  }
+  if (walker > INT32_MAX || slot > INT32_MAX) return fail(ISING_E_RANGE, "too many walkers");
+  g.R = walker;
+  g.slots = slot;
+  g.spin_words = word;
+  // Buckets: systems sharing (S, ring, degree class); one launch each.
+  std::map<std::tuple<int32_t, int32_t, int32_t>, std::vector<int32_t>> groups;
+  for (size_t s = 0; s < hs.size(); ++s) {
+    const int32_t dc = hs[s].deg <= 0 ? 0 : hs[s].deg <= 2 ? 2 : hs[s].deg <= 4 ? 4 : hs[s].deg <= 6 ? 6 : 8;
+    groups[{hs[s].S, hs[s].ring, dc}].push_back((int32_t)s);
+  }
+  for (auto &kv : groups) {
+    Bucket b{};
+    b.S = std::get<0>(kv.first);
+    b.ring = std::get<1>(kv.first);
+    b.deg = std::get<2>(kv.first);
+    int32_t maxw = 0, Kmax = 1;
+    for (int32_t s : kv.second) {
+      const SysInfo &si = g.sys[s];
+      maxw = std::max(maxw, lds_words_per_walker(ring_words(si.S, si.F), si.WW));
+      Kmax = std::max(Kmax, si.K);
+      b.F = std::max(b.F, si.F);
+      b.M = std::max(b.M, si.M);
+    }
+    b.G = choose_G(b.S, Kmax, maxw);
+    b.threads = ((b.G * b.S + 63) / 64) * 64;
+    b.lds = (size_t)b.G * maxw * 4;
+    b.tile0 = (int32_t)g.tiles.size();
+    for (int32_t s : kv.second)
+      for (int32_t w0 = 0; w0 < g.sys[s].K; w0 += b.G)
+        g.tiles.push_back(Tile{s, w0, std::min(b.G, g.sys[s].K - w0), 0});
+    b.ntiles = (int32_t)g.tiles.size() - b.tile0;
+    if (b.lds > 160 * 1024) return fail(ISING_E_RANGE, "a walker needs %zu bytes of LDS (> 160 KiB)", b.lds);
+    g.buckets.push_back(b);
+  }
+  return ISING_OK;
+}
+
+static int32_t build_all(const ising_system_desc *sys, int32_t n_sys, std::vector<SysHost> &hs) {
+  if (!sys || n_sys < 1) return fail(ISING_E_INVAL, "need at least one system");
+  hs.resize(n_sys);
+  for (int32_t s = 0; s < n_sys; ++s) {
+    int32_t rc = build_system(sys[s], s, hs[s]);
+    if (rc) return rc;
+  }
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys, size_t *dev_bytes) {
+  if (!dev_bytes) return fail(ISING_E_INVAL, "dev_bytes is NULL");
+  std::vector<SysHost> hs;
+  int32_t rc = build_all(sys, n_sys, hs);
+  if (rc) return rc;
+  ising_graph g;
+  rc = plan(hs, g);
+  if (rc) return rc;
+  int64_t ntm = 0;
+  for (auto &h : hs) ntm += h.S;
+  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R).total;
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys, void *dev_tables,
+                                    size_t bytes, void *stream, ising_graph **out) {
+  if (!out || !dev_tables) return fail(ISING_E_INVAL, "load_graph: NULL argument");
+  if (((uintptr_t)dev_tables & 255u) != 0) return fail(ISING_E_INVAL, "dev_tables must be 256-byte aligned");
+  *out = nullptr;
+  std::vector<SysHost> hs;
+  int32_t rc = build_all(sys, n_sys, hs);
+  if (rc) return rc;
+  ising_graph *g = new ising_graph();
+  rc = plan(hs, *g);
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  int64_t ntm = 0;
+  for (auto &h : hs) ntm += h.S;
+  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R);
+  if (bytes < L.total) {
+    delete g;
+    return fail(ISING_E_SIZE, "dev_tables has %zu bytes, needs %zu", bytes, L.total);
+  }
+  std::vector<uint8_t> host(L.total, 0);
+  memcpy(host.data() + L.sys, g->sys.data(), sizeof(SysInfo) * g->sys.size());
+  {
+    TmplSpin *t = (TmplSpin *)(host.data() + L.tmpl);
+    for (auto &h : hs) {
+      memcpy(t, h.tmpl.data(), sizeof(TmplSpin) * h.S);
+      t += h.S;
+    }
+    uint32_t *thr = (uint32_t *)(host.data() + L.thr);
+    double *bt = (double *)(host.data() + L.beta);
+    for (auto &h : hs)
+      for (int32_t k = 0; k < h.K; ++k) {
+        rc = ising_threshold_row(h.beta[k], kThrRow - 1, thr);
+        if (rc) {
+          delete g;
+          return rc;
+        }
+        thr += kThrRow;
+        *bt++ = h.beta[k];
+      }
+  }
+  memcpy(host.data() + L.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size());
+  memcpy(host.data() + L.wsys, g->walker_sys.data(), sizeof(int32_t) * g->walker_sys.size());
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dev_tables, host.data(), L.total, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "load_graph copy");
+  }
+  uint8_t *base = (uint8_t *)dev_tables;
+  g->dev.sys = (const SysInfo *)(base + L.sys);
+  g->dev.tmpl = (const TmplSpin *)(base + L.tmpl);
+  g->dev.thr = (const uint32_t *)(base + L.thr);
+  g->dev.beta = (const double *)(base + L.beta);
+  g->dev.tiles = (const Tile *)(base + L.tiles);
+  g->dev.walker_sys = (const int32_t *)(base + L.wsys);
+  g->bytes = L.total;
+  *out = g;
+  return ISING_OK;
+}
+
+extern "C" void ising_free_graph(ising_graph *g) { delete g; }
+
+extern "C" int32_t ising_graph_info(const ising_graph *g, int64_t *out, int32_t n) {
+  if (!g || !out || n < 0) return fail(ISING_E_INVAL, "graph_info: bad arguments");
+  const int64_t v[6] = {g->n_sys, g->R, g->slots, g->spin_words, g->attempts, g->max_levels};
+  for (int32_t i = 0; i < n && i < 6; ++i) out[i] = v[i];
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row_words) {
+  if (!g || !spin_word || !row_words) return fail(ISING_E_INVAL, "spin_layout: NULL argument");
+  for (int32_t s = 0; s < g->n_sys; ++s) {
+    const SysInfo &si = g->sys[s];
+    row_words[s] = si.SW;
+    for (int32_t k = 0; k < si.K; ++k) spin_word[si.walker0 + k] = si.spin_word0 + (int64_t)k * si.WW;
+  }
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_state_sizes(const ising_graph *g, int64_t *c) {
+  if (!g || !c) return fail(ISING_E_INVAL, "state_sizes: NULL argument");
+  c[0] = g->spin_words;
+  c[1] = g->R * kMtN;
+  c[2] = g->R;
+  c[3] = g->R;
+  c[4] = g->slots;
+  c[5] = (int64_t)g->n_sys * kMtN;
+  c[6] = g->R;
+  c[7] = g->slots;
+  c[8] = g->slots;
+  c[9] = ISING_N_STATS;
+  return ISING_OK;
+}
+
+static int32_t check_state(const ising_state *st) {
+  if (!st || !st->spins || !st->mt || !st->energy || !st->temp_of || !st->walker_at || !st->swap_mt ||
+      !st->flips || !st->swap_att || !st->swap_acc || !st->stats)
+    return fail(ISING_E_INVAL, "state has a NULL buffer");
+  return ISING_OK;
+}
+
+static DevState dev_state(const ising_state *st) {
+  return DevState{st->spins, st->mt, st->energy, st->temp_of, st->walker_at, st->swap_mt,
+                  st->flips, st->swap_att, st->swap_acc, st->stats};
+}
+
+extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *walker_seeds,
+                                    const uint32_t *swap_seeds, void *stream) {
+  if (!g || !walker_seeds || !swap_seeds) return fail(ISING_E_INVAL, "init_state: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  DevState d = dev_state(st);
+  // Seeds go to word 0 of each window; the seed kernel expands them.
+  HIP_TRY(hipMemcpy2DAsync(st->mt, kMtN * sizeof(uint32_t), walker_seeds, sizeof(uint32_t), sizeof(uint32_t),
+                           (size_t)g->R, hipMemcpyHostToDevice, s),
+          "init_state seeds");
+  HIP_TRY(hipMemcpy2DAsync(st->swap_mt, kMtN * sizeof(uint32_t), swap_seeds, sizeof(uint32_t),
+                           sizeof(uint32_t), (size_t)g->n_sys, hipMemcpyHostToDevice, s),
+          "init_state swap seeds");
+  HIP_TRY(hipStreamSynchronize(s), "init_state sync");
+  HIP_TRY(launch_seed(d, (int32_t)g->R, g->n_sys, s), "seed kernel");
+  HIP_TRY(hipMemsetAsync(st->flips, 0, sizeof(uint64_t) * g->R, s), "init_state clear");
+  HIP_TRY(hipMemsetAsync(st->swap_att, 0, sizeof(uint64_t) * g->slots, s), "init_state clear");
+  HIP_TRY(hipMemsetAsync(st->swap_acc, 0, sizeof(uint64_t) * g->slots, s), "init_state clear");
+  HIP_TRY(hipMemsetAsync(st->stats, 0, sizeof(uint64_t) * ISING_N_STATS, s), "init_state clear");
+  HIP_TRY(launch_labels(g->dev, d, (int32_t)g->R, g->n_sys, s), "labels kernel");
+  for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, 0, 1, s), "initial spins");
+  HIP_TRY(launch_observables(g->dev, d, (int32_t)g->R, nullptr, 1, s), "initial energies");
+  st->sweeps = 0;
+  st->rounds = 0;
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,
+                               int32_t *e_series, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "sweep: NULL graph");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  if (n_sweeps < 0 || swap_every < 0) return fail(ISING_E_INVAL, "sweep: negative count");
+  if (st->sweeps < 0) return fail(ISING_E_STATE, "sweep: state not initialised");
+  hipStream_t s = (hipStream_t)stream;
+  DevState d = dev_state(st);
+  int32_t done = 0;
+  while (done < n_sweeps) {
+    // Sweeps until the next swap round (or the end, or the next record).
+    int32_t seg = n_sweeps - done;
+    if (swap_every > 0) {
+      const int64_t to_swap = swap_every - (st->sweeps % swap_every);
+      seg = (int32_t)std::min<int64_t>(seg, to_swap);
+    }
+    if (e_series) seg = 1;
+    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
+    st->sweeps += seg;
+    done += seg;
+    int32_t *row = e_series ? e_series + (size_t)(done - 1) * g->slots : nullptr;
+    if (swap_every > 0 && st->sweeps % swap_every == 0) {
+      HIP_TRY(launch_swap(g->dev, d, g->n_sys, (int32_t)(st->rounds & 1), row, s), "swap kernel");
+      st->rounds += 1;
+    } else if (row) {
+      HIP_TRY(launch_record(g->dev, d, g->n_sys, row, s), "record kernel");
+    }
+  }
+  return ISING_OK;
+}
+
+extern "C" int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "pt_swap: NULL graph");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  if (parity != 0 && parity != 1) return fail(ISING_E_INVAL, "pt_swap: parity must be 0 or 1");
+  HIP_TRY(launch_swap(g->dev, dev_state(st), g->n_sys, parity, nullptr, (hipStream_t)stream), "swap kernel");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *obs, void *stream) {
+  if (!g || !obs) return fail(ISING_E_INVAL, "observables: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  HIP_TRY(launch_observables(g->dev, dev_state(st), (int32_t)g->R, obs, 0, (hipStream_t)stream),
+          "observables kernel");
+  return ISING_OK;
+}

@@ -1,0 +1,92 @@
+// Internal layout shared by the host side and the kernels of libising.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ising {
+
+constexpr int kMtN = 624;       // MT19937 words
+constexpr int kMtM = 397;       // MT19937 middle offset
+constexpr int kMtLag = 227;     // kMtN - kMtM: words generated without a chain
+constexpr int kThrRow = 64;     // threshold words per temperature slot (d = 0..63)
+constexpr int kMaxDeg = 8;      // in-slice neighbours in a template record
+
+// One system, as the kernels see it.
+struct SysInfo {
+  int32_t S, M, ring, F;   // spins per slice, slices, ring flag, schedule depth
+  int32_t SW, WW;          // words per slice row, words per walker
+  int32_t K, walker0;      // walkers (= slots), global index of walker 0
+  int64_t spin_word0;      // first spin word of walker 0
+  int32_t tmpl0;           // first template record
+  int32_t thr0;            // first threshold row (K rows of kThrRow words)
+  int32_t slot0;           // first global slot
+  int32_t deg;             // max in-slice degree of the template
+};
+
+// Template spin q: in-slice neighbours with their couplings, field, tau coupling,
+// level offset.  Unused neighbour entries point at q itself with J = 0.
+struct TmplSpin {
+  int16_t nbr[kMaxDeg];
+  int8_t J[kMaxDeg];
+  int8_t h, Jtau;
+  uint8_t f, deg;
+  int32_t pad;
+};
+static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
+
+// One workgroup of the sweep: `nw` walkers of system `sys` starting at `w0`.
+struct Tile {
+  int32_t sys, w0, nw, pad;
+};
+
+// Launch geometry of one bucket of tiles (systems with the same S and kernel variant).
+struct Bucket {
+  int32_t S, Z, WW, G;      // template size, MT ring words, words per walker, walkers per tile
+  int32_t ring, deg, F, M;  // variant selectors and the common shape
+  int32_t tile0, ntiles;    // tiles [tile0, tile0 + ntiles)
+  int32_t threads;          // workgroup size
+  size_t lds;               // dynamic LDS bytes
+};
+
+// Words of LDS per walker slot in a sweep workgroup.
+__host__ __device__ inline int32_t lds_words_per_walker(int32_t Z, int32_t WW) { return Z + WW + kThrRow + 4; }
+
+// Ring size: room for the F+1 chunks in flight plus the 624-word look-back,
+// rounded up to whole chunks of S words.
+__host__ __device__ inline int32_t ring_words(int32_t S, int32_t F) {
+  int32_t extra = (kMtN + S - 1) / S;
+  return S * (F + 1 + extra);
+}
+
+struct DevTables {
+  const SysInfo *sys;
+  const TmplSpin *tmpl;
+  const uint32_t *thr;   // [slots][kThrRow]
+  const double *beta;    // [slots]
+  const Tile *tiles;
+  const int32_t *walker_sys;  // [R] system of each walker
+};
+
+struct DevState {
+  uint32_t *spins, *mt;
+  int32_t *energy, *temp_of, *walker_at;
+  uint32_t *swap_mt;
+  uint64_t *flips, *swap_att, *swap_acc, *stats;
+};
+
+// Kernel launchers (each returns the hipError_t of the launch).
+// Expand the seed stored in word 0 of every walker / swap stream window into
+// the 624 init_genrand words.
+hipError_t launch_seed(const DevState &s, int32_t R, int32_t n_sys, hipStream_t st);
+hipError_t launch_sweep(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
+                        int32_t init_mode, hipStream_t st);
+hipError_t launch_swap(const DevTables &t, const DevState &s, int32_t n_sys, int32_t parity,
+                       int32_t *e_row, hipStream_t st);
+hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, int32_t *e_row,
+                         hipStream_t st);
+hipError_t launch_observables(const DevTables &t, const DevState &s, int32_t R, int32_t *obs,
+                              int32_t set_energy, hipStream_t st);
+hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32_t n_sys,
+                         hipStream_t st);
+
+}  // namespace ising

@@ -59,7 +59,7 @@ extern "C" int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr)
 }
 
 struct SysHost {
-  int32_t S, M, ring, F, deg, dmax, K;
+  int32_t S, M, ring, F, deg, dmax, K, cell;
   std::vector<TmplSpin> tmpl;
   std::vector<double> beta;
 };
@@ -133,6 +133,39 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
     t.Jtau = (int8_t)jt;
     t.f = (uint8_t)fq;
     t.deg = (uint8_t)nb[q].size();
+    t.jpack = 0;
+  }
+  // Cell templates: every spin is joined to the four spins of the other half of
+  // its aligned group of eight (a K4,4 unit cell); those four go first, in
+  // partner order, with their 2J packed into one word.
+  bool cell = S % 8 == 0;
+  for (int32_t q = 0; q < S && cell; ++q) {
+    const int32_t p0 = (q & ~7) + ((q & 4) ^ 4);
+    for (int32_t i = 0; i < 4 && cell; ++i) {
+      bool found = false;
+      for (auto &p : nb[q]) found |= p.first == p0 + i;
+      cell = found;
+    }
+  }
+  out.cell = cell ? 1 : 0;
+  if (cell) {
+    for (int32_t q = 0; q < S; ++q) {
+      const int32_t p0 = (q & ~7) + ((q & 4) ^ 4);
+      std::vector<std::pair<int32_t, int8_t>> order;
+      for (int32_t i = 0; i < 4; ++i)
+        for (auto &p : nb[q])
+          if (p.first == p0 + i) order.push_back(p);
+      for (auto &p : nb[q])
+        if (p.first < p0 || p.first >= p0 + 4) order.push_back(p);
+      TmplSpin &t = out.tmpl[q];
+      uint32_t pack = 0;
+      for (size_t j = 0; j < order.size(); ++j) {
+        t.nbr[j] = (int16_t)order[j].first;
+        t.J[j] = order[j].second;
+        if (j < 4) pack |= (uint32_t)(uint8_t)(int8_t)(2 * order[j].second) << (8 * j);
+      }
+      t.jpack = (int32_t)pack;
+    }
   }
   if (F > 255) return fail(ISING_E_RANGE, "system %d: schedule depth %d exceeds 255", idx, F);
   out.F = F;
@@ -210,8 +243,9 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.M = h.M;
     si.ring = h.ring;
     si.F = h.F;
-    si.SW = (h.S + 31) / 32;
-    si.WW = si.SW * h.M;
+    const int32_t sw = (h.S + 31) / 32;
+    si.RS = (sw > 1 && sw % 2 == 0) ? sw + 1 : sw;
+    si.WW = si.RS * h.M;
     si.K = h.K;
     si.walker0 = (int32_t)walker;
     si.spin_word0 = word;
@@ -219,6 +253,8 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.thr0 = (int32_t)slot;
     si.slot0 = (int32_t)slot;
     si.deg = h.deg;
+    si.cell = h.cell;
+    si.nx = h.deg - (h.cell ? 4 : 0);
     walker += h.K;
     slot += h.K;
     word += (int64_t)si.WW * h.K;
@@ -231,17 +267,19 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
   g.R = walker;
   g.slots = slot;
   g.spin_words = word;
-  // Buckets: systems sharing (S, ring, degree class); one launch each.
-  std::map<std::tuple<int32_t, int32_t, int32_t>, std::vector<int32_t>> groups;
+  // Buckets: systems sharing (S, ring, cell, neighbour class); one launch each.
+  std::map<std::tuple<int32_t, int32_t, int32_t, int32_t>, std::vector<int32_t>> groups;
   for (size_t s = 0; s < hs.size(); ++s) {
-    const int32_t dc = hs[s].deg <= 0 ? 0 : hs[s].deg <= 2 ? 2 : hs[s].deg <= 4 ? 4 : hs[s].deg <= 6 ? 6 : 8;
-    groups[{hs[s].S, hs[s].ring, dc}].push_back((int32_t)s);
+    const int32_t nx = g.sys[s].nx;
+    const int32_t nc = nx <= 0 ? 0 : nx <= 2 ? 2 : nx <= 4 ? 4 : nx <= 6 ? 6 : 8;
+    groups[{hs[s].S, hs[s].ring, hs[s].cell, nc}].push_back((int32_t)s);
   }
   for (auto &kv : groups) {
     Bucket b{};
     b.S = std::get<0>(kv.first);
     b.ring = std::get<1>(kv.first);
-    b.deg = std::get<2>(kv.first);
+    b.cell = std::get<2>(kv.first);
+    b.nx = std::get<3>(kv.first);
     int32_t maxw = 0, Kmax = 1;
     for (int32_t s : kv.second) {
       const SysInfo &si = g.sys[s];
@@ -364,7 +402,7 @@ extern "C" int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, i
   if (!g || !spin_word || !row_words) return fail(ISING_E_INVAL, "spin_layout: NULL argument");
   for (int32_t s = 0; s < g->n_sys; ++s) {
     const SysInfo &si = g->sys[s];
-    row_words[s] = si.SW;
+    row_words[s] = si.RS;
     for (int32_t k = 0; k < si.K; ++k) spin_word[si.walker0 + k] = si.spin_word0 + (int64_t)k * si.WW;
   }
   return ISING_OK;

@@ -121,9 +121,9 @@ __global__ void __launch_bounds__(256) observables_kernel(DevTables T, DevState 
                                                           int32_t set_energy) {
   const int r = blockIdx.x;
   const SysInfo sy = T.sys[T.walker_sys[r]];
-  const int S = sy.S, M = sy.M, SW = sy.SW;
+  const int S = sy.S, M = sy.M, RS = sy.RS;
   const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)(r - sy.walker0) * sy.WW;
-  auto spin = [&](int m, int q) { return (int)((sp[m * SW + (q >> 5)] >> (q & 31)) & 1u) * 2 - 1; };
+  auto spin = [&](int m, int q) { return (int)((sp[m * RS + (q >> 5)] >> (q & 31)) & 1u) * 2 - 1; };
   long long e = 0, mag = 0;
   const int N = S * M;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {

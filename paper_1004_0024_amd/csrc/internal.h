@@ -14,23 +14,27 @@ constexpr int kMaxDeg = 8;      // in-slice neighbours in a template record
 // One system, as the kernels see it.
 struct SysInfo {
   int32_t S, M, ring, F;   // spins per slice, slices, ring flag, schedule depth
-  int32_t SW, WW;          // words per slice row, words per walker
+  int32_t RS, WW;          // words per slice row (odd when > 1: no LDS bank aliasing), per walker
   int32_t K, walker0;      // walkers (= slots), global index of walker 0
   int64_t spin_word0;      // first spin word of walker 0
   int32_t tmpl0;           // first template record
   int32_t thr0;            // first threshold row (K rows of kThrRow words)
   int32_t slot0;           // first global slot
   int32_t deg;             // max in-slice degree of the template
+  int32_t cell;            // 1: every spin's first 4 neighbours are the other half of its 8-spin cell
+  int32_t nx;              // neighbours handled one by one (deg, or deg - 4 for cell templates)
 };
 
 // Template spin q: in-slice neighbours with their couplings, field, tau coupling,
-// level offset.  Unused neighbour entries point at q itself with J = 0.
+// level offset.  Unused neighbour entries point at q itself with J = 0.  For a
+// cell template nbr[0..3] are the partners q' = (q & ~7) + ((q & 4) ^ 4) + i and
+// jpack holds their 2J as four signed bytes (byte i for partner i).
 struct TmplSpin {
   int16_t nbr[kMaxDeg];
   int8_t J[kMaxDeg];
   int8_t h, Jtau;
   uint8_t f, deg;
-  int32_t pad;
+  int32_t jpack;
 };
 static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
 
@@ -42,14 +46,19 @@ struct Tile {
 // Launch geometry of one bucket of tiles (systems with the same S and kernel variant).
 struct Bucket {
   int32_t S, Z, WW, G;      // template size, MT ring words, words per walker, walkers per tile
-  int32_t ring, deg, F, M;  // variant selectors and the common shape
+  int32_t ring, nx, F, M;   // variant selectors and the common shape
+  int32_t cell, pad;
   int32_t tile0, ntiles;    // tiles [tile0, tile0 + ntiles)
   int32_t threads;          // workgroup size
   size_t lds;               // dynamic LDS bytes
 };
 
 // Words of LDS per walker slot in a sweep workgroup.
-__host__ __device__ inline int32_t lds_words_per_walker(int32_t Z, int32_t WW) { return Z + WW + kThrRow + 4; }
+// LDS words per walker slot: MT ring (with a kMtN-word shadow in front, so
+// look-back reads never wrap), spins, threshold row, reduction slots.
+__host__ __device__ inline int32_t lds_words_per_walker(int32_t Z, int32_t WW) {
+  return Z + kMtN + WW + kThrRow + 4;
+}
 
 // Ring size: room for the F+1 chunks in flight plus the 624-word look-back,
 // rounded up to whole chunks of S words.

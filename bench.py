@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="B")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
@@ -63,7 +66,19 @@ def main():
 
     wl = make_workload(args.config)
     g = pa.Graph(wl.systems)
+    tuned = None
+    if not args.no_autotune:
+        scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+        trials = g.autotune(scratch, reps=3)
+        del scratch
+        tuned = {"trials": len(trials), "shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")}
+                                                   for b in g.buckets()]}
     st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     n_sw = wl.n_sweeps
@@ -92,6 +107,17 @@ def main():
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     sweep_ms = [evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for k in range(args.steps) for t in range(n_sw)]
+    # The same step as one captured HIP graph (sweep + swap kernels, no host work).
+    rep = st.capture(n_sw, swap_every=1)
+    rep.launch()
+    rep.stream.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(rep.stream)
+    for _ in range(max(1, args.steps // 2)):
+        rep.launch()
+    g1.record(rep.stream)
+    rep.stream.synchronize()
+    graph_ms = g0.elapsed_time(g1) / max(1, args.steps // 2)
     avg_sweep_s = sum(sweep_ms) / len(sweep_ms) / 1e3
     attempts_step = g.attempts_per_sweep * n_sw
     value = attempts_step * args.steps / (ms / 1e3)
@@ -117,6 +143,9 @@ def main():
                      "kernel": "sweep_kernel", "kernel_avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_attempt": BYTES_PER_ATTEMPT},
         "wall_s_timed": wall,
+        "graph_replay": {"ms_per_step": graph_ms, "value": g.attempts_per_sweep * n_sw / (graph_ms / 1e3)},
+        "launch_shapes": tuned,
+        "sweep_kernel_ms": {"mean": avg_sweep_s * 1e3, "min": min(sweep_ms), "max": max(sweep_ms)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -114,6 +114,21 @@ int32_t ising_graph_info(const ising_graph *g, int64_t *out, int32_t n);
  * of walker r is +1 iff that bit is set.  Host arrays [R] and [n_sys].      */
 int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row_words);
 
+/* Launch shapes.  Systems with the same template size and kernel variant
+ * form a bucket, swept by one launch.  A walker's template columns are spread
+ * over `tpw` threads (a power of two; a thread visits ceil(S/tpw) <= 8
+ * columns per level; tpw <= 64 keeps a walker inside one wavefront) and a
+ * workgroup holds `walkers_per_group` walkers.  Shapes change speed only: the
+ * chain is the same for every shape.  bucket_info writes, in this order:
+ *   S, systems, walkers, attempts per sweep, tpw, walkers per group, columns
+ *   per thread, workgroup threads, LDS bytes per workgroup, workgroups.
+ * set_launch returns ISING_E_RANGE for a shape that does not fit (threads,
+ * LDS, columns per thread) and leaves the bucket unchanged.                  */
+int32_t ising_n_buckets(const ising_graph *g);
+int32_t ising_bucket_info(const ising_graph *g, int32_t bucket, int64_t *out, int32_t n);
+int32_t ising_set_launch(ising_graph *g, int32_t bucket, int32_t tpw, int32_t walkers_per_group,
+                         void *stream);
+
 /* Device buffers of the chain (caller-owned).  Element counts come from
  * ising_state_sizes; walker r of system s is walker r - first(s) there.    */
 typedef struct {
@@ -156,6 +171,30 @@ int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *
  * slot after each sweep and its swap round.                                  */
 int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,
                     int32_t *e_series, void *stream);
+
+/* Captured sweep loops.  ising_capture records, on a non-default `stream`,
+ * exactly the launches ising_sweep(g, st, n_sweeps, swap_every, e_series)
+ * would make from the state's current counters (nothing runs and the state is
+ * unchanged) and instantiates them as one HIP graph.  ising_replay_launch
+ * enqueues the graph and advances st->sweeps / st->rounds; it returns
+ * ISING_E_STATE unless `st` has the captured buffers and the same swap phase
+ * (rounds mod 2, sweeps mod swap_every).  e_series, if given, is rewritten by
+ * every replay.  The handle owns only the HIP graph objects.                 */
+typedef struct ising_replay ising_replay;
+int32_t ising_capture(const ising_graph *g, const ising_state *st, int32_t n_sweeps, int32_t swap_every,
+                      int32_t *e_series, void *stream, ising_replay **out);
+int32_t ising_replay_launch(ising_replay *r, ising_state *st, void *stream);
+void ising_replay_free(ising_replay *r);
+
+/* Autotuner: for every bucket, time each admissible launch shape (tpw a power
+ * of two, walkers per group 1, 2, 4 .. 32) with HIP events over `reps`
+ * single-sweep launches on `scratch` (an initialised state of this graph whose
+ * chain it advances), then keep the fastest shape.  Optionally writes one row
+ * {bucket, tpw, walkers_per_group, microseconds per sweep} per trial to
+ * report[report_rows][4].  Returns the number of rows written (>= 0) or an
+ * error code.  Synchronous.                                                  */
+int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream, int64_t *report,
+                       int32_t report_rows);
 
 /* One swap round of every system with the given parity (0: pairs (0,1),(2,3)..;
  * 1: (1,2),(3,4)..).  Does not change st->rounds.                             */

@@ -67,6 +67,13 @@ def lib():
             "ising_threshold_row": ([C.c_double, i32, P], i32),
             "ising_level_offsets": ([P, P, P], i32),
             "ising_last_error": ([], C.c_char_p),
+            "ising_n_buckets": ([P], i32),
+            "ising_bucket_info": ([P, i32, P, i32], i32),
+            "ising_set_launch": ([P, i32, i32, i32, P], i32),
+            "ising_capture": ([P, P, i32, i32, P, P, P], i32),
+            "ising_replay_launch": ([P, P, P], i32),
+            "ising_replay_free": ([P], None),
+            "ising_autotune": ([P, P, i32, P, P, i32], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -156,6 +163,28 @@ class Graph:
     def handle(self):
         return self._handle
 
+    _BUCKET_KEYS = ["S", "systems", "walkers", "attempts", "tpw", "G", "cpt", "threads", "lds", "tiles"]
+
+    def buckets(self):
+        out = []
+        for b in range(lib().ising_n_buckets(self._handle)):
+            v = np.zeros(10, np.int64)
+            _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), 10))
+            out.append(dict(zip(self._BUCKET_KEYS, (int(x) for x in v))))
+        return out
+
+    def set_launch(self, bucket, tpw, walkers_per_group):
+        _check(lib().ising_set_launch(self._handle, int(bucket), int(tpw), int(walkers_per_group), _stream()))
+
+    def autotune(self, scratch_state, reps=3):
+        """Pick the fastest launch shape per bucket, timed on `scratch_state`."""
+        rows = 64 * max(1, len(self.buckets()))
+        rep = np.zeros((rows, 4), np.int64)
+        n = lib().ising_autotune(self._handle, C.byref(scratch_state._s), int(reps), _stream(), _np_ptr(rep), rows)
+        if n < 0:
+            _check(n)
+        return [dict(bucket=int(r[0]), tpw=int(r[1]), G=int(r[2]), us_per_sweep=int(r[3])) for r in rep[:n]]
+
 
 class State:
     """Chain state in torch device tensors, walker-major."""
@@ -175,7 +204,7 @@ class State:
         self.t = {}
         for name, n in zip(self._FIELDS, counts):
             self.t[name] = torch.zeros(max(int(n), 1), dtype=dt[name], device=dev)
-        self._s = StateStruct(*[C.c_void_p(self.t[n].data_ptr()) for n in self._FIELDS], 0, -1)
+        self._s = StateStruct(*[C.c_void_p(self.t[n].data_ptr()) for n in self._FIELDS], -1, 0)
 
     @property
     def sweeps(self):
@@ -200,6 +229,10 @@ class State:
         _check(lib().ising_sweep(self.graph.handle, C.byref(self._s), int(n_sweeps), int(swap_every),
                                  C.c_void_p(e.data_ptr()) if e is not None else None, _stream()))
         return e
+
+    def capture(self, n_sweeps, swap_every=1, stream=None, record=False):
+        """A HIP graph of `n_sweeps` sweeps from the current counters (see Replay)."""
+        return Replay(self, n_sweeps, swap_every, stream, record)
 
     def swap(self, parity):
         _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))
@@ -235,3 +268,31 @@ class State:
 
     def swap_window(self):
         return self.host("swap_mt").view(np.uint32).reshape(self.graph.n_sys, 624)
+
+
+class Replay:
+    """A captured sweep loop; launch() replays it on the capture stream."""
+
+    def __init__(self, state, n_sweeps, swap_every, stream, record):
+        import torch
+        self.state = state
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.e = None
+        if record:
+            self.e = torch.zeros((n_sweeps, state.graph.slots), dtype=torch.int32,
+                                 device=state.graph.tables.device)
+        self._h = C.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        _check(lib().ising_capture(state.graph.handle, C.byref(state._s), int(n_sweeps), int(swap_every),
+                                   C.c_void_p(self.e.data_ptr()) if self.e is not None else None,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h)))
+
+    def launch(self):
+        _check(lib().ising_replay_launch(self._h, C.byref(self.state._s), C.c_void_p(self.stream.cuda_stream)))
+        return self.e
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.ising_replay_free(h)
+            self._h = None

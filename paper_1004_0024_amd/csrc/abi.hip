@@ -59,8 +59,9 @@ extern "C" int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr)
 }
 
 struct SysHost {
-  int32_t S, M, ring, F, deg, dmax, K, cell;
+  int32_t S, M, ring, F, deg, dmax, K, cell, FW;
   std::vector<TmplSpin> tmpl;
+  std::vector<uint32_t> fifo;  // (queue base << 8) | log2(depth) per template spin
   std::vector<double> beta;
 };
 
@@ -169,6 +170,16 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
   }
   if (F > 255) return fail(ISING_E_RANGE, "system %d: schedule depth %d exceeds 255", idx, F);
   out.F = F;
+  out.fifo.assign(S, 0);
+  int32_t fw = 0;
+  for (int32_t q = 0; q < S; ++q) {
+    const int32_t dq = fifo_depth(f[q]);
+    int32_t lg = 0;
+    while ((1 << lg) < dq) ++lg;
+    out.fifo[q] = ((uint32_t)fw << 8) | (uint32_t)lg;
+    fw += dq;
+  }
+  out.FW = fw;
   out.beta.assign(d.beta, d.beta + d.n_temps);
   return ISING_OK;
 }
@@ -192,6 +203,7 @@ struct ising_graph {
   std::vector<SysInfo> sys;
   std::vector<Tile> tiles;
   std::vector<Bucket> buckets;
+  std::vector<std::vector<int32_t>> bucket_sys;  // systems of each bucket
   std::vector<int32_t> walker_sys;
   DevTables dev{};
   size_t bytes = 0;
@@ -200,16 +212,21 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, thr, beta, tiles, wsys, total;
+  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, total;
 };
 
+// Device tables.  Room for one tile per walker, so any launch shape can be
+// installed later without reallocating.
 static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R) {
   Layout L{};
   size_t o = 0;
+  n_tiles = std::max(n_tiles, R);
   L.sys = o;
   o = align256(o + sizeof(SysInfo) * n_sys);
   L.tmpl = o;
   o = align256(o + sizeof(TmplSpin) * n_tmpl);
+  L.fifo = o;
+  o = align256(o + sizeof(uint32_t) * n_tmpl);
   L.thr = o;
   o = align256(o + sizeof(uint32_t) * kThrRow * slots);
   L.beta = o;
@@ -222,14 +239,43 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   return L;
 }
 
-// Walkers per workgroup for a template of S spins: aim at ~512 threads and a
-// per-workgroup LDS budget that leaves room for two workgroups per CU.
-static int32_t choose_G(int32_t S, int32_t Kmax, int32_t ldsw_per_walker) {
-  int32_t G = std::max(1, 512 / S);
-  G = std::min(G, std::max(1, 1024 / S));
+// Launch shape of a bucket: `tpw` threads per walker (a power of two; each
+// thread owns ceil(S/tpw) <= 8 columns) and G walkers per workgroup.
+static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
+  if (tpw < 1 || (tpw & (tpw - 1)) != 0 || tpw > 1024) return fail(ISING_E_RANGE, "tpw must be a power of two <= 1024");
+  const int32_t need = (b.S + tpw - 1) / tpw;
+  int32_t cpt = 1;
+  while (cpt < need) cpt <<= 1;
+  if (cpt > 8) return fail(ISING_E_RANGE, "tpw=%d leaves %d columns per thread (max 8)", tpw, need);
+  if (G < 1) return fail(ISING_E_RANGE, "G must be >= 1");
   G = std::min(G, Kmax);
-  while (G > 1 && (size_t)G * ldsw_per_walker * 4 > 80 * 1024) --G;
-  return G;
+  if ((int64_t)G * tpw > 1024) return fail(ISING_E_RANGE, "G*tpw exceeds 1024 threads");
+  const size_t lds = ((size_t)G * b.walker_words + b.S) * 4;
+  if (lds > 160 * 1024) return fail(ISING_E_RANGE, "launch shape needs %zu bytes of LDS (> 160 KiB)", lds);
+  b.tpw = tpw;
+  b.cpt = cpt;
+  b.G = G;
+  b.threads = std::max(64, ((G * tpw + 63) / 64) * 64);
+  b.lds = lds;
+  return ISING_OK;
+}
+
+// Default shape (measured on MI355X for 8x8 and 4x4 cell templates): at most
+// two columns per thread, up to 256 threads and ~40 KiB of LDS per workgroup.
+static void default_shape(int32_t S, int32_t walker_words, int32_t &tpw, int32_t &G) {
+  int32_t p = 8;
+  while (p < S) p <<= 1;
+  tpw = p >= 256 ? p / 2 : p;
+  G = std::max(1, 256 / tpw);
+  while (G > 1 && (size_t)G * walker_words * 4 > 40 * 1024) --G;
+}
+
+static void tile_bucket(ising_graph &g, Bucket &b, const std::vector<int32_t> &systems) {
+  b.tile0 = (int32_t)g.tiles.size();
+  for (int32_t s : systems)
+    for (int32_t w0 = 0; w0 < g.sys[s].K; w0 += b.G)
+      g.tiles.push_back(Tile{s, w0, std::min(b.G, g.sys[s].K - w0), 0});
+  b.ntiles = (int32_t)g.tiles.size() - b.tile0;
 }
 
 static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
@@ -255,6 +301,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.deg = h.deg;
     si.cell = h.cell;
     si.nx = h.deg - (h.cell ? 4 : 0);
+    si.fifo_words = h.FW;
     walker += h.K;
     slot += h.K;
     word += (int64_t)si.WW * h.K;
@@ -283,21 +330,17 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     int32_t maxw = 0, Kmax = 1;
     for (int32_t s : kv.second) {
       const SysInfo &si = g.sys[s];
-      maxw = std::max(maxw, lds_words_per_walker(ring_words(si.S, si.F), si.WW));
+      maxw = std::max(maxw, walker_lds_words(si.S, si.WW, si.fifo_words));
       Kmax = std::max(Kmax, si.K);
-      b.F = std::max(b.F, si.F);
-      b.M = std::max(b.M, si.M);
     }
-    b.G = choose_G(b.S, Kmax, maxw);
-    b.threads = ((b.G * b.S + 63) / 64) * 64;
-    b.lds = (size_t)b.G * maxw * 4;
-    b.tile0 = (int32_t)g.tiles.size();
-    for (int32_t s : kv.second)
-      for (int32_t w0 = 0; w0 < g.sys[s].K; w0 += b.G)
-        g.tiles.push_back(Tile{s, w0, std::min(b.G, g.sys[s].K - w0), 0});
-    b.ntiles = (int32_t)g.tiles.size() - b.tile0;
-    if (b.lds > 160 * 1024) return fail(ISING_E_RANGE, "a walker needs %zu bytes of LDS (> 160 KiB)", b.lds);
+    b.walker_words = maxw;
+    int32_t tpw, G;
+    default_shape(b.S, maxw, tpw, G);
+    int32_t rc = shape_bucket(b, tpw, G, Kmax);
+    if (rc) return rc;
+    tile_bucket(g, b, kv.second);
     g.buckets.push_back(b);
+    g.bucket_sys.push_back(kv.second);
   }
   return ISING_OK;
 }
@@ -368,6 +411,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
         *bt++ = h.beta[k];
       }
   }
+  {
+    uint32_t *fo = (uint32_t *)(host.data() + L.fifo);
+    for (auto &h : hs) {
+      memcpy(fo, h.fifo.data(), sizeof(uint32_t) * h.S);
+      fo += h.S;
+    }
+  }
   memcpy(host.data() + L.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size());
   memcpy(host.data() + L.wsys, g->walker_sys.data(), sizeof(int32_t) * g->walker_sys.size());
   hipStream_t st = (hipStream_t)stream;
@@ -384,12 +434,50 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.beta = (const double *)(base + L.beta);
   g->dev.tiles = (const Tile *)(base + L.tiles);
   g->dev.walker_sys = (const int32_t *)(base + L.wsys);
+  g->dev.fifo = (const uint32_t *)(base + L.fifo);
   g->bytes = L.total;
   *out = g;
   return ISING_OK;
 }
 
 extern "C" void ising_free_graph(ising_graph *g) { delete g; }
+
+extern "C" int32_t ising_n_buckets(const ising_graph *g) { return g ? (int32_t)g->buckets.size() : 0; }
+
+extern "C" int32_t ising_bucket_info(const ising_graph *g, int32_t bucket, int64_t *out, int32_t n) {
+  if (!g || !out || bucket < 0 || bucket >= (int32_t)g->buckets.size())
+    return fail(ISING_E_INVAL, "bucket_info: bad arguments");
+  const Bucket &b = g->buckets[bucket];
+  int64_t walkers = 0, attempts = 0;
+  for (int32_t s : g->bucket_sys[bucket]) {
+    walkers += g->sys[s].K;
+    attempts += (int64_t)g->sys[s].K * g->sys[s].S * g->sys[s].M;
+  }
+  const int64_t v[10] = {b.S, (int64_t)g->bucket_sys[bucket].size(), walkers, attempts, b.tpw, b.G,
+                         b.cpt, b.threads, (int64_t)b.lds, b.ntiles};
+  for (int32_t i = 0; i < n && i < 10; ++i) out[i] = v[i];
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_set_launch(ising_graph *g, int32_t bucket, int32_t tpw, int32_t walkers_per_group,
+                                    void *stream) {
+  if (!g || bucket < 0 || bucket >= (int32_t)g->buckets.size())
+    return fail(ISING_E_INVAL, "set_launch: bad bucket");
+  Bucket b = g->buckets[bucket];
+  int32_t Kmax = 1;
+  for (int32_t s : g->bucket_sys[bucket]) Kmax = std::max(Kmax, g->sys[s].K);
+  int32_t rc = shape_bucket(b, tpw, walkers_per_group, Kmax);
+  if (rc) return rc;
+  g->buckets[bucket] = b;
+  g->tiles.clear();
+  for (size_t i = 0; i < g->buckets.size(); ++i) tile_bucket(*g, g->buckets[i], g->bucket_sys[i]);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size(),
+                         hipMemcpyHostToDevice, st),
+          "set_launch copy");
+  HIP_TRY(hipStreamSynchronize(st), "set_launch sync");
+  return ISING_OK;
+}
 
 extern "C" int32_t ising_graph_info(const ising_graph *g, int64_t *out, int32_t n) {
   if (!g || !out || n < 0) return fail(ISING_E_INVAL, "graph_info: bad arguments");
@@ -463,6 +551,33 @@ extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const
   return ISING_OK;
 }
 
+// Enqueue n_sweeps sweeps (and the swap rounds due) starting from the
+// counters *sweeps / *rounds, advancing them.
+static int32_t enqueue_sweeps(const ising_graph *g, const DevState &d, int64_t *sweeps, int64_t *rounds,
+                              int32_t n_sweeps, int32_t swap_every, int32_t *e_series, hipStream_t s) {
+  int32_t done = 0;
+  while (done < n_sweeps) {
+    // Sweeps until the next swap round (or the end, or the next record).
+    int32_t seg = n_sweeps - done;
+    if (swap_every > 0) {
+      const int64_t to_swap = swap_every - (*sweeps % swap_every);
+      seg = (int32_t)std::min<int64_t>(seg, to_swap);
+    }
+    if (e_series) seg = 1;
+    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
+    *sweeps += seg;
+    done += seg;
+    int32_t *row = e_series ? e_series + (size_t)(done - 1) * g->slots : nullptr;
+    if (swap_every > 0 && *sweeps % swap_every == 0) {
+      HIP_TRY(launch_swap(g->dev, d, g->n_sys, (int32_t)(*rounds & 1), row, s), "swap kernel");
+      *rounds += 1;
+    } else if (row) {
+      HIP_TRY(launch_record(g->dev, d, g->n_sys, row, s), "record kernel");
+    }
+  }
+  return ISING_OK;
+}
+
 extern "C" int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,
                                int32_t *e_series, void *stream) {
   if (!g) return fail(ISING_E_INVAL, "sweep: NULL graph");
@@ -470,29 +585,146 @@ extern "C" int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_
   if (rc) return rc;
   if (n_sweeps < 0 || swap_every < 0) return fail(ISING_E_INVAL, "sweep: negative count");
   if (st->sweeps < 0) return fail(ISING_E_STATE, "sweep: state not initialised");
+  return enqueue_sweeps(g, dev_state(st), &st->sweeps, &st->rounds, n_sweeps, swap_every, e_series,
+                        (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Captured sweep loops (hipGraph)
+// ---------------------------------------------------------------------------
+struct ising_replay {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t sweeps0 = 0, rounds0 = 0, dsweeps = 0, drounds = 0;
+  int32_t swap_every = 0;
+  DevState dev{};
+};
+
+extern "C" int32_t ising_capture(const ising_graph *g, const ising_state *st, int32_t n_sweeps,
+                                 int32_t swap_every, int32_t *e_series, void *stream, ising_replay **out) {
+  if (!g || !out) return fail(ISING_E_INVAL, "capture: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  if (n_sweeps < 1 || swap_every < 0) return fail(ISING_E_INVAL, "capture: need n_sweeps >= 1");
+  if (!stream) return fail(ISING_E_INVAL, "capture: needs a non-default stream");
+  if (st->sweeps < 0) return fail(ISING_E_STATE, "capture: state not initialised");
   hipStream_t s = (hipStream_t)stream;
-  DevState d = dev_state(st);
-  int32_t done = 0;
-  while (done < n_sweeps) {
-    // Sweeps until the next swap round (or the end, or the next record).
-    int32_t seg = n_sweeps - done;
-    if (swap_every > 0) {
-      const int64_t to_swap = swap_every - (st->sweeps % swap_every);
-      seg = (int32_t)std::min<int64_t>(seg, to_swap);
-    }
-    if (e_series) seg = 1;
-    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
-    st->sweeps += seg;
-    done += seg;
-    int32_t *row = e_series ? e_series + (size_t)(done - 1) * g->slots : nullptr;
-    if (swap_every > 0 && st->sweeps % swap_every == 0) {
-      HIP_TRY(launch_swap(g->dev, d, g->n_sys, (int32_t)(st->rounds & 1), row, s), "swap kernel");
-      st->rounds += 1;
-    } else if (row) {
-      HIP_TRY(launch_record(g->dev, d, g->n_sys, row, s), "record kernel");
-    }
+  ising_replay *r = new ising_replay();
+  r->sweeps0 = st->sweeps;
+  r->rounds0 = st->rounds;
+  r->swap_every = swap_every;
+  r->dev = dev_state(st);
+  int64_t sw = st->sweeps, ro = st->rounds;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete r;
+    return hip_fail(e, "capture begin");
   }
+  rc = enqueue_sweeps(g, r->dev, &sw, &ro, n_sweeps, swap_every, e_series, s);
+  e = hipStreamEndCapture(s, &r->graph);
+  if (rc) {
+    if (r->graph) hipGraphDestroy(r->graph);
+    delete r;
+    return rc;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (r->graph) hipGraphDestroy(r->graph);
+    delete r;
+    return hip_fail(e, "capture end / instantiate");
+  }
+  r->dsweeps = sw - st->sweeps;
+  r->drounds = ro - st->rounds;
+  *out = r;
   return ISING_OK;
+}
+
+extern "C" int32_t ising_replay_launch(ising_replay *r, ising_state *st, void *stream) {
+  if (!r || !st) return fail(ISING_E_INVAL, "replay: NULL argument");
+  if (st->spins != r->dev.spins || st->mt != r->dev.mt || st->energy != r->dev.energy)
+    return fail(ISING_E_STATE, "replay: captured for other state buffers");
+  if ((st->rounds & 1) != (r->rounds0 & 1) ||
+      (r->swap_every > 0 && st->sweeps % r->swap_every != r->sweeps0 % r->swap_every))
+    return fail(ISING_E_STATE, "replay: the state's swap phase differs from the captured one");
+  HIP_TRY(hipGraphLaunch(r->exec, (hipStream_t)stream), "replay launch");
+  st->sweeps += r->dsweeps;
+  st->rounds += r->drounds;
+  return ISING_OK;
+}
+
+extern "C" void ising_replay_free(ising_replay *r) {
+  if (!r) return;
+  if (r->exec) hipGraphExecDestroy(r->exec);
+  if (r->graph) hipGraphDestroy(r->graph);
+  delete r;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time every admissible launch shape of every bucket on a scratch
+// state (single-sweep launches, as in a swap-every-sweep loop) and keep the
+// fastest.  The chain does not depend on the shape.
+// ---------------------------------------------------------------------------
+extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream,
+                                  int64_t *report, int32_t report_rows) {
+  if (!g) return fail(ISING_E_INVAL, "autotune: NULL graph");
+  int32_t rc = check_state(scratch);
+  if (rc) return rc;
+  if (reps < 1) reps = 3;
+  hipStream_t s = (hipStream_t)stream;
+  DevState d = dev_state(scratch);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "autotune event");
+  HIP_TRY(hipEventCreate(&e1), "autotune event");
+  int32_t row = 0;
+  for (size_t bi = 0; bi < g->buckets.size(); ++bi) {
+    int32_t Kmax = 1;
+    for (int32_t sy : g->bucket_sys[bi]) Kmax = std::max(Kmax, g->sys[sy].K);
+    const Bucket orig = g->buckets[bi];
+    Bucket best = orig;
+    float best_ms = -1.f;
+    for (int32_t tpw = 8; tpw <= 1024; tpw <<= 1) {
+      for (int32_t G = 1; G <= 32; G <<= 1) {
+        Bucket b = orig;
+        if (shape_bucket(b, tpw, G, Kmax) != ISING_OK || b.G != G) continue;
+        g->buckets[bi] = b;
+        g->tiles.clear();
+        for (size_t i = 0; i < g->buckets.size(); ++i) tile_bucket(*g, g->buckets[i], g->bucket_sys[i]);
+        HIP_TRY(hipMemcpyAsync((void *)g->dev.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size(),
+                               hipMemcpyHostToDevice, s),
+                "autotune tiles");
+        HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], 1, 0, s), "autotune warm-up");
+        HIP_TRY(hipEventRecord(e0, s), "autotune event");
+        for (int32_t k = 0; k < reps; ++k) HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], 1, 0, s), "autotune trial");
+        HIP_TRY(hipEventRecord(e1, s), "autotune event");
+        HIP_TRY(hipEventSynchronize(e1), "autotune sync");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "autotune time");
+        ms /= (float)reps;
+        if (report && row < report_rows) {
+          int64_t *o = report + (size_t)row * 4;
+          o[0] = (int64_t)bi;
+          o[1] = tpw;
+          o[2] = G;
+          o[3] = (int64_t)(ms * 1000.f);  // microseconds per sweep
+          ++row;
+        }
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best = g->buckets[bi];
+        }
+      }
+    }
+    g->buckets[bi] = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  g->tiles.clear();
+  for (size_t i = 0; i < g->buckets.size(); ++i) tile_bucket(*g, g->buckets[i], g->bucket_sys[i]);
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size(),
+                         hipMemcpyHostToDevice, s),
+          "autotune tiles");
+  HIP_TRY(hipStreamSynchronize(s), "autotune sync");
+  return row;
 }
 
 extern "C" int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream) {

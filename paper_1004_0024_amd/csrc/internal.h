@@ -23,6 +23,8 @@ struct SysInfo {
   int32_t deg;             // max in-slice degree of the template
   int32_t cell;            // 1: every spin's first 4 neighbours are the other half of its 8-spin cell
   int32_t nx;              // neighbours handled one by one (deg, or deg - 4 for cell templates)
+  int32_t fifo_words;      // per walker: sum over template spins of their uniform-queue depths
+  int32_t pad;
 };
 
 // Template spin q: in-slice neighbours with their couplings, field, tau coupling,
@@ -45,26 +47,32 @@ struct Tile {
 
 // Launch geometry of one bucket of tiles (systems with the same S and kernel variant).
 struct Bucket {
-  int32_t S, Z, WW, G;      // template size, MT ring words, words per walker, walkers per tile
-  int32_t ring, nx, F, M;   // variant selectors and the common shape
-  int32_t cell, pad;
+  int32_t S, G, tpw, cpt;   // template size, walkers per tile, threads per walker, columns per thread
+  int32_t ring, nx, cell;   // kernel variant
   int32_t tile0, ntiles;    // tiles [tile0, tile0 + ntiles)
   int32_t threads;          // workgroup size
+  int32_t walker_words;     // LDS words per walker slot (max over the bucket's systems)
   size_t lds;               // dynamic LDS bytes
 };
 
-// Words of LDS per walker slot in a sweep workgroup.
-// LDS words per walker slot: MT ring (with a kMtN-word shadow in front, so
-// look-back reads never wrap), spins, threshold row, reduction slots.
-__host__ __device__ inline int32_t lds_words_per_walker(int32_t Z, int32_t WW) {
-  return Z + kMtN + WW + kThrRow + 4;
+// Generator ring: the 624-word look-back of MT19937 plus one chunk of S words,
+// rounded up to whole chunks.  A kMtN-word copy of its top slots sits in front
+// of slot 0, so look-back reads never wrap.
+__host__ __device__ inline int32_t gen_ring_words(int32_t S) { return S * (1 + (kMtN + S - 1) / S); }
+
+// Uniform queue of template spin q: the uniforms of its column wait there from
+// generation (one level before the slice starts) until its visit f(q) levels
+// later; f(q) + 2 slots, rounded up to a power of two.
+__host__ __device__ inline int32_t fifo_depth(int32_t f) {
+  int32_t d = 2;
+  while (d < f + 2) d <<= 1;
+  return d;
 }
 
-// Ring size: room for the F+1 chunks in flight plus the 624-word look-back,
-// rounded up to whole chunks of S words.
-__host__ __device__ inline int32_t ring_words(int32_t S, int32_t F) {
-  int32_t extra = (kMtN + S - 1) / S;
-  return S * (F + 1 + extra);
+// LDS words of one walker slot: generator ring (+ shadow), uniform queues,
+// spins, threshold row, reduction slots.
+__host__ __device__ inline int32_t walker_lds_words(int32_t S, int32_t WW, int32_t FW) {
+  return gen_ring_words(S) + kMtN + FW + WW + kThrRow + 4;
 }
 
 struct DevTables {
@@ -74,6 +82,7 @@ struct DevTables {
   const double *beta;    // [slots]
   const Tile *tiles;
   const int32_t *walker_sys;  // [R] system of each walker
+  const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
 };
 
 struct DevState {

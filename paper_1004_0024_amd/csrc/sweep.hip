@@ -10,234 +10,269 @@
 // level(i) < level(j) (in-slice: f grows along the edge; tau: m grows; the
 // wrap edge (0,q)-(M-1,q) joins levels f and M-1+f), so processing the levels
 // in order, each level in parallel, reproduces the sequential sweep bit for
-// bit.  One thread owns one template column q of one walker and visits its M
-// spins at levels f(q) .. f(q)+M-1; a sweep takes M + F - 1 levels,
-// F = max f + 1.  This is the paper's interlacing of layers over threads
-// (Section 3.2, Figure 12c) with a skew that keeps the sequential order
-// instead of an even/odd reordering.
+// bit.  A template column q of a walker visits its M spins at levels
+// f(q) .. f(q)+M-1; a sweep takes M + F - 1 levels, F = max f + 1.  This is
+// the paper's interlacing of layers over threads (Section 3.2, Figure 12c)
+// with a skew that keeps the sequential order instead of an even/odd
+// reordering.
+//
+// Work split: a walker has TPW threads; thread t owns the columns
+// q = c*TPW + t, c < CPT, and visits them one after another inside a level
+// (independent attempts, so their latencies overlap).  When TPW <= 64 a
+// walker lives inside one wavefront and a level ends with a wavefront fence
+// instead of a workgroup barrier.
 //
 // Data in LDS for the whole launch, per walker:
 //  - spins, one bit each, slice rows of RS words (RS odd when > 1, so rows of
 //    different slices fall in different LDS banks);
-//  - the walker's MT19937 words in a ring of Z words: word n (counted from the
-//    launch's first window word) lives in slot (n + delta) mod Z, chunks of S
-//    words aligned to slot multiples of S; chunk g holds the uniforms of slice
-//    m = g mod M of sweep g / M.  A copy of the last kMtN slots sits in front of
-//    slot 0, so the generator's look-back reads (624, 623 and 227 words back)
-//    never wrap;
-//  - its threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1 (d = 0 -> all).
+//  - the MT19937 generator ring: word n (counted from the launch's first
+//    window word) in slot (n + delta) mod Zg, chunks of S words aligned to
+//    slot multiples of S, with a copy of the top kMtN slots in front of slot 0
+//    so the look-back reads (624, 623 and 227 words back) never wrap;
+//  - one uniform queue per template column: chunk g (the uniforms of slice
+//    m = g mod M of sweep g / M) is generated one level before its first
+//    consumer and each word is also copied to the queue of its column, slot
+//    g mod depth, where it waits until the column reaches that slice;
+//  - the walker's threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1.
 // The local field of a spin is pulled from its neighbours' bits when the spin
 // is visited (no field array, no conflicting neighbour updates).  For cell
 // templates (K4,4 unit cells) the four in-cell neighbours are the other nibble
-// of the spin's own byte and are summed with one 4-way byte dot product.  The
-// MT19937 chunk for the next slice is generated cooperatively by the walker's
-// threads one level ahead (a generator thread chains the words 227 apart).
+// of the spin's own byte, summed with one 4-way byte dot product.
 #include "internal.h"
 #include "mt19937.h"
 
 namespace ising {
 
-template <int NX, bool CELL, bool RING>
-__global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, int32_t tile0,
-                                                     int32_t G, int32_t n_sweeps, int32_t init_mode) {
+template <bool WS>
+__device__ __forceinline__ void level_sync() {
+  if (WS) {
+    // A walker's threads are one wavefront: its LDS operations execute in
+    // order, so only the compiler must not move them across the level.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int NX, bool CELL, bool RING, int CPT, bool WS>
+__global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, int32_t tile0, int32_t G,
+                                                     int32_t TPW, int32_t PW, int32_t n_sweeps,
+                                                     int32_t init_mode) {
   extern __shared__ uint32_t lds[];
   const Tile tile = T.tiles[tile0 + blockIdx.x];
   const SysInfo sy = T.sys[tile.sys];
-  const int S = sy.S, M = sy.M, RS = sy.RS, WW = sy.WW;
+  const int S = sy.S, M = sy.M, RS = sy.RS, WW = sy.WW, FW = sy.fifo_words;
   const int F = init_mode ? 1 : sy.F;
-  const int Z = ring_words(S, sy.F);
-  const int ZP = Z + kMtN;  // physical ring words per walker (shadow + ring)
+  const int Zg = gen_ring_words(S);
+  const int ZP = Zg + kMtN;
   const int nw = tile.nw;
   const int tid = threadIdx.x, nthr = blockDim.x;
 
-  uint32_t *ringp = lds;                          // [G][ZP]
-  uint32_t *sp = ringp + G * ZP;                  // [G][WW]
-  uint32_t *thr = sp + G * WW;                    // [G][kThrRow]
-  int32_t *acc = (int32_t *)(thr + G * kThrRow);  // [G][4]
+  // walker slot layout: [shadow | generator ring][queues][spins][thr][acc]
+  uint32_t *fifo_tab = lds + G * PW;  // [S] shared by the tile's walkers
+  auto wbase = [&](int w) { return lds + w * PW; };
 
   const int delta = (S - (kMtN % S)) % S;  // chunk-aligned slots
-  const int c0 = (kMtN + delta) / S;       // slot chunk of chunk 0
-  const int zs = Z - kMtN;                 // slots >= zs also live in the shadow
+  const int kg = Zg / S;
+  const int c0 = (kMtN + delta) / S;       // slot chunk of chunk 0 (= kg - 1)
+  const int zs = Zg - kMtN;                // slots >= zs also live in the shadow
 
   // ---- load the walkers' state ----
   for (int i = tid; i < nw * kMtN; i += nthr) {
     const int w = i / kMtN, j = i - w * kMtN;
     const int r = sy.walker0 + tile.w0 + w;
     const uint32_t v = St.mt[(size_t)r * kMtN + j];
-    uint32_t *rb = ringp + w * ZP + kMtN;
+    uint32_t *g = wbase(w) + kMtN;
     const int x = j + delta;
-    rb[x] = v;
-    if (x >= zs) rb[x - Z] = v;
+    g[x] = v;
+    if (x >= zs) g[x - Zg] = v;
   }
   for (int i = tid; i < nw * WW; i += nthr) {
     const int w = i / WW, j = i - w * WW;
-    sp[w * WW + j] = init_mode ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j];
+    wbase(w)[ZP + FW + j] = init_mode ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j];
   }
   if (!init_mode) {
     for (int i = tid; i < nw * kThrRow; i += nthr) {
       const int w = i / kThrRow, j = i - w * kThrRow;
       const int slot = St.temp_of[sy.walker0 + tile.w0 + w];
-      thr[w * kThrRow + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
+      wbase(w)[ZP + FW + WW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
     }
   }
-  if (tid < G * 4) acc[tid] = 0;
+  for (int i = tid; i < S; i += nthr) fifo_tab[i] = T.fifo[sy.tmpl0 + i];
+  for (int i = tid; i < nw * 4; i += nthr) wbase(i / 4)[ZP + FW + WW + kThrRow + (i & 3)] = 0u;
 
-  // ---- this thread's column ----
-  const int gw = tid / S, q = tid - gw * S;
+  // ---- this thread's walker and columns ----
+  const int gw = tid / TPW, t = tid - gw * TPW;
   const bool live = gw < nw;
-  const int qo = q >> 5;
-  const int qb = q & 31;
-  const uint32_t qbit = 1u << qb;
-  int xoff[NX > 0 ? NX : 1], xbit[NX > 0 ? NX : 1], xj2[NX > 0 ? NX : 1];
-  int base = 0, jt = 0, f = 0, jpack = 0;
-  if (live) {
-    const TmplSpin ts = T.tmpl[sy.tmpl0 + q];
+  uint32_t *wb = wbase(live ? gw : 0);
+  uint32_t *gring = wb + kMtN;  // logical slot 0
+  uint32_t *fq = wb + ZP;
+  uint32_t *sp = fq + FW;
+  const uint32_t *thw = sp + WW;
+  int32_t *acc = (int32_t *)(thw + kThrRow);
+
+  int qo[CPT], qb[CPT], base[CPT], jt[CPT], f[CPT], jpack[CPT], fb[CPT], fmask[CPT];
+  int xoff[CPT][NX > 0 ? NX : 1], xbit[CPT][NX > 0 ? NX : 1], xj2[CPT][NX > 0 ? NX : 1];
+  bool col[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int q = c * TPW + t;
+    col[c] = live && q < S;
+    const int qq0 = col[c] ? q : 0;
+    qo[c] = qq0 >> 5;
+    qb[c] = qq0 & 31;
+    const TmplSpin ts = T.tmpl[sy.tmpl0 + qq0];
     int sumJ = 0;
     if (CELL) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) sumJ += ts.J[j];
-      jpack = ts.jpack;
+      jpack[c] = ts.jpack;
+    } else {
+      jpack[c] = 0;
     }
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const int qq = ts.nbr[(CELL ? 4 : 0) + j];
-      xoff[j] = (qq >> 5) - qo;
-      xbit[j] = qq & 31;
-      xj2[j] = 2 * (int)ts.J[(CELL ? 4 : 0) + j];
+      xoff[c][j] = (qq >> 5) - qo[c];
+      xbit[c][j] = qq & 31;
+      xj2[c][j] = 2 * (int)ts.J[(CELL ? 4 : 0) + j];
       sumJ += ts.J[(CELL ? 4 : 0) + j];
     }
-    jt = ts.Jtau;
-    f = ts.f;
+    jt[c] = ts.Jtau;
+    f[c] = ts.f;
     // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms: the constant part is `base`.
-    base = (int)ts.h - sumJ - (RING ? 2 * jt : 0);
+    base[c] = (int)ts.h - sumJ - (RING ? 2 * (int)ts.Jtau : 0);
+    const uint32_t fw = T.fifo[sy.tmpl0 + qq0];
+    fb[c] = (int)(fw >> 8);
+    fmask[c] = (1 << (fw & 0xff)) - 1;
   }
-  const int nibpos = (qb & ~3) ^ 4;  // partner nibble inside the own word
-  uint32_t *spw = sp + (live ? gw : 0) * WW + qo;  // own word of row 0
-  uint32_t *rw = ringp + (live ? gw : 0) * ZP + kMtN;
-  const uint32_t *thw = thr + (live ? gw : 0) * kThrRow;
 
-  // Generator role.  S <= 227: thread (gw, q) makes word q of each chunk.
-  // S > 227: thread t < G*227 makes words j, j+227, j+454 of walker t/227.
-  const bool chained = S > kMtLag;
-  const int gen_w = chained ? tid / kMtLag : gw;
-  const int gen_j = chained ? tid - gen_w * kMtLag : q;
-  const bool gen_live = gen_w < nw && (chained || live);
-  uint32_t *grb = ringp + (gen_w < G ? gen_w : 0) * ZP + kMtN;
-
-  auto put = [&](int x, uint32_t v) {
-    grb[x] = v;
-    if (x >= zs) grb[x - Z] = v;
-  };
-  auto gen_chunk = [&](int gslot) {  // gslot: ring slot of word 0 of the chunk
-    if (!gen_live) return;
-    if (!chained) {
-      const int x = gslot + gen_j;
-      put(x, mt_next_word(grb[x - kMtN], grb[x - kMtN + 1], grb[x - kMtLag]));
-    } else {
-      uint32_t prev = 0;
+  // Generator: chain heads j < min(S, 227) go round-robin to the walker's
+  // threads; a head makes words j, j+227, j+454 (< S) of each chunk.
+  const int heads = S < kMtLag ? S : kMtLag;
+  auto gen_chunk = [&](int gslot, int chunk) {
+    if (!live) return;
+    for (int j = t; j < heads; j += TPW) {
+      uint32_t a[3], b[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int o = gen_j + i * kMtLag;
+      for (int s = 0; s < 3; ++s) {
+        const int x = gslot + j + s * kMtLag;
+        if (j + s * kMtLag < S) {
+          a[s] = gring[x - kMtN];
+          b[s] = gring[x - kMtN + 1];
+        }
+      }
+      uint32_t prev = gring[gslot + j - kMtLag];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int o = j + s * kMtLag;
         if (o < S) {
           const int x = gslot + o;
-          const uint32_t c = i == 0 ? grb[x - kMtLag] : prev;
-          prev = mt_next_word(grb[x - kMtN], grb[x - kMtN + 1], c);
-          put(x, prev);
+          prev = mt_next_word(a[s], b[s], prev);
+          gring[x] = prev;
+          if (x >= zs) gring[x - Zg] = prev;
+          const uint32_t fw = fifo_tab[o];
+          fq[(int)(fw >> 8) + (chunk & ((1 << (fw & 0xff)) - 1))] = prev;
         }
       }
     }
   };
+  auto advance = [Zg, S](int x) {
+    x += S;
+    return x >= Zg ? x - Zg : x;
+  };
 
   __syncthreads();
 
-  int gslot = c0 * S;  // slot of the next chunk to generate
-  auto advance = [Z, S](int x) {
-    x += S;
-    return x >= Z ? x - Z : x;
-  };
-  int cpos = c0 * S + q;  // slot of this thread's next uniform
-  auto cadvance = [Z, S](int x) {
-    x += S;
-    return x >= Z ? x - Z : x;
-  };
+  int gslot = c0 * S;  // generator slot of the next chunk
   int dE = 0, nfl = 0;
   uint32_t st_steps = 0, st_flip = 0;
 
-  gen_chunk(gslot);
+  gen_chunk(gslot, 0);
   gslot = advance(gslot);
-  __syncthreads();
+  level_sync<WS>();
 
   if (init_mode) {
     // Initial spins: bit (m, q) = top bit of output m*S + q.
     for (int m = 0; m < M; ++m) {
       if (m + 1 < M) {
-        gen_chunk(gslot);
+        gen_chunk(gslot, m + 1);
         gslot = advance(gslot);
       }
-      if (live) {
-        const uint32_t u = mt_temper(rw[cpos]);
-        if (u >> 31) atomicOr(spw + m * RS, qbit);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        if (col[c]) {
+          const uint32_t u = mt_temper(fq[fb[c] + (m & fmask[c])]);
+          if (u >> 31) atomicOr(sp + m * RS + qo[c], 1u << qb[c]);
+        }
       }
-      cpos = cadvance(cpos);
-      __syncthreads();
+      level_sync<WS>();
     }
   } else {
     const int levels = M + F - 1;
     const int last_row = (M - 1) * RS;
-    for (int t = 0; t < n_sweeps; ++t) {
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+      const int chunk0 = sw * M;
       for (int lv = 0; lv < levels; ++lv) {
-        const int m = lv - f;
-        const bool active = live && m >= 0 && m < M;
-        bool flip = false;
-        if (active) {
-          const int rc = (int)__umul24((unsigned)m, (unsigned)RS);
-          const int rp = m == 0 ? last_row : rc - RS;
-          const int rn = m == M - 1 ? 0 : rc + RS;
-          uint32_t *own_p = spw + rc;
-          const uint32_t own = *own_p;
-          int hs = base;
-          if (CELL) {
-            const uint32_t nib = __builtin_amdgcn_ubfe(own, (unsigned)nibpos, 4u);
-            const uint32_t spread = __umul24(nib, 0x00204081u) & 0x01010101u;  // bit i -> byte i
-            hs = __builtin_amdgcn_sdot4((int)spread, jpack, hs, false);
-          }
 #pragma unroll
-          for (int j = 0; j < NX; ++j)
-            hs += __builtin_amdgcn_sbfe((int)own_p[xoff[j]], (unsigned)xbit[j], 1u) & xj2[j];
-          const int bp = (int)__builtin_amdgcn_ubfe(spw[rp], (unsigned)qb, 1u);
-          const int bn = (int)__builtin_amdgcn_ubfe(spw[rn], (unsigned)qb, 1u);
-          if (RING) {
-            hs += 2 * jt * (bp + bn);
-          } else {
-            const int jp = m > 0 ? jt : 0, jn = m < M - 1 ? jt : 0;
-            hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
+        for (int c = 0; c < CPT; ++c) {
+          const int m = lv - f[c];
+          const bool active = col[c] && m >= 0 && m < M;
+          bool flip = false;
+          if (active) {
+            const int rc = (int)__umul24((unsigned)m, (unsigned)RS) + qo[c];
+            const int rpp = m == 0 ? last_row + qo[c] : rc - RS;
+            const int rnn = m == M - 1 ? qo[c] : rc + RS;
+            uint32_t *own_p = sp + rc;
+            const uint32_t own = *own_p;
+            const uint32_t u0 = fq[fb[c] + ((chunk0 + m) & fmask[c])];
+            int hs = base[c];
+            if (CELL) {
+              const uint32_t nib = __builtin_amdgcn_ubfe(own, (unsigned)((qb[c] & ~3) ^ 4), 4u);
+              const uint32_t spread = __umul24(nib, 0x00204081u) & 0x01010101u;  // bit i -> byte i
+              hs = __builtin_amdgcn_sdot4((int)spread, jpack[c], hs, false);
+            }
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+              hs += __builtin_amdgcn_sbfe((int)own_p[xoff[c][j]], (unsigned)xbit[c][j], 1u) & xj2[c][j];
+            const int bp = (int)__builtin_amdgcn_ubfe(sp[rpp], (unsigned)qb[c], 1u);
+            const int bn = (int)__builtin_amdgcn_ubfe(sp[rnn], (unsigned)qb[c], 1u);
+            if (RING) {
+              hs += 2 * jt[c] * (bp + bn);
+            } else {
+              const int jp = m > 0 ? jt[c] : 0, jn = m < M - 1 ? jt[c] : 0;
+              hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
+            }
+            const int sb = (int)__builtin_amdgcn_ubfe(own, (unsigned)qb[c], 1u);
+            const int d = sb ? hs : -hs;  // s_i * h_eff_i; flipping costs 2d
+            const uint32_t u = mt_temper(u0);
+            flip = u <= thw[d > 0 ? d : 0];
+            if (flip) {
+              atomicXor(own_p, 1u << qb[c]);
+              dE += 2 * d;
+              ++nfl;
+            }
           }
-          const int sb = (int)__builtin_amdgcn_ubfe(own, (unsigned)qb, 1u);
-          const int d = sb ? hs : -hs;  // s_i * h_eff_i; flipping costs 2d
-          const uint32_t u = mt_temper(rw[cpos]);
-          flip = u <= thw[d > 0 ? d : 0];
-          if (flip) {
-            atomicXor(own_p, qbit);
-            dE += 2 * d;
-            ++nfl;
-          }
-          cpos = cadvance(cpos);
+          st_steps += __ballot(active) != 0ull;
+          st_flip += __ballot(flip) != 0ull;
         }
-        st_steps += __ballot(active) != 0ull;
-        st_flip += __ballot(flip) != 0ull;
-        if (lv + 1 < M || (lv == M - 1 && t + 1 < n_sweeps)) {
-          gen_chunk(gslot);
+        if (lv + 1 < M) {
+          gen_chunk(gslot, chunk0 + lv + 1);
+          gslot = advance(gslot);
+        } else if (lv == M - 1 && sw + 1 < n_sweeps) {
+          gen_chunk(gslot, chunk0 + M);
           gslot = advance(gslot);
         }
-        __syncthreads();
+        level_sync<WS>();
       }
     }
   }
 
   // ---- write back ----
   if (live && !init_mode) {
-    atomicAdd(&acc[gw * 4 + 0], dE);
-    atomicAdd(&acc[gw * 4 + 1], nfl);
+    atomicAdd(&acc[0], dE);
+    atomicAdd(&acc[1], nfl);
   }
   if (!init_mode && (tid & 63) == 0) {
     atomicAdd((unsigned long long *)&St.stats[1], (unsigned long long)st_steps);
@@ -248,44 +283,66 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   __syncthreads();
   for (int i = tid; i < nw * WW; i += nthr) {
     const int w = i / WW, j = i - w * WW;
-    St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j] = sp[w * WW + j];
+    St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j] = wbase(w)[ZP + FW + j];
   }
   const long long consumed = init_mode ? (long long)M * S : (long long)n_sweeps * M * S;
   for (int i = tid; i < nw * kMtN; i += nthr) {
     const int w = i / kMtN, j = i - w * kMtN;
     const int r = sy.walker0 + tile.w0 + w;
-    St.mt[(size_t)r * kMtN + j] = ringp[w * ZP + kMtN + (int)((consumed + j + delta) % Z)];
+    St.mt[(size_t)r * kMtN + j] = wbase(w)[kMtN + (int)((consumed + j + delta) % Zg)];
   }
   if (!init_mode && tid < nw) {
     const int r = sy.walker0 + tile.w0 + tid;
-    St.energy[r] += acc[tid * 4 + 0];
-    St.flips[r] += (unsigned long long)(uint32_t)acc[tid * 4 + 1];
+    const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + WW + kThrRow);
+    St.energy[r] += a[0];
+    St.flips[r] += (unsigned long long)(uint32_t)a[1];
   }
 }
 
-template <int NX, bool CELL, bool RING>
+template <int NX, bool CELL, bool RING, int CPT, bool WS>
 static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bucket &b,
                                  int32_t n_sweeps, int32_t init_mode, hipStream_t st) {
-  auto kern = sweep_kernel<NX, CELL, RING>;
-  if (b.lds > 64 * 1024) {
+  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS>;
+  // Allow the whole LDS once per instantiation (outside any stream capture
+  // after the first launch of a variant).
+  static bool lds_limit_set = false;
+  if (!lds_limit_set && b.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)b.lds);
+                                       160 * 1024);
     if (e != hipSuccess) return e;
+    lds_limit_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(b.ntiles), dim3(b.threads), b.lds, st, t, s, b.tile0, b.G, n_sweeps,
-                     init_mode);
+  hipLaunchKernelGGL(kern, dim3(b.ntiles), dim3(b.threads), b.lds, st, t, s, b.tile0, b.G, b.tpw,
+                     b.walker_words, n_sweeps, init_mode);
   return hipGetLastError();
+}
+
+template <int NX, bool CELL, bool RING>
+static hipError_t launch_cpt(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
+                             int32_t init_mode, hipStream_t st) {
+  const bool ws = b.tpw <= 64;
+  switch (b.cpt) {
+    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true>(t, s, b, n_sweeps, init_mode, st)
+                      : launch_variant<NX, CELL, RING, 1, false>(t, s, b, n_sweeps, init_mode, st);
+    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true>(t, s, b, n_sweeps, init_mode, st)
+                      : launch_variant<NX, CELL, RING, 2, false>(t, s, b, n_sweeps, init_mode, st);
+    case 4: return ws ? launch_variant<NX, CELL, RING, 4, true>(t, s, b, n_sweeps, init_mode, st)
+                      : launch_variant<NX, CELL, RING, 4, false>(t, s, b, n_sweeps, init_mode, st);
+    case 8: return ws ? launch_variant<NX, CELL, RING, 8, true>(t, s, b, n_sweeps, init_mode, st)
+                      : launch_variant<NX, CELL, RING, 8, false>(t, s, b, n_sweeps, init_mode, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <bool CELL, bool RING>
 static hipError_t launch_nx(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
                             int32_t init_mode, hipStream_t st) {
   switch (b.nx) {
-    case 0: return launch_variant<0, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 2: return launch_variant<2, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 4: return launch_variant<4, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 6: return launch_variant<6, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 8: return launch_variant<8, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
+    case 0: return launch_cpt<0, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
+    case 2: return launch_cpt<2, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
+    case 4: return launch_cpt<4, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
+    case 6: if (!CELL) return launch_cpt<6, CELL, RING>(t, s, b, n_sweeps, init_mode, st); break;
+    case 8: if (!CELL) return launch_cpt<8, CELL, RING>(t, s, b, n_sweeps, init_mode, st); break;
   }
   return hipErrorInvalidValue;
 }
@@ -293,11 +350,9 @@ static hipError_t launch_nx(const DevTables &t, const DevState &s, const Bucket 
 hipError_t launch_sweep(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
                         int32_t init_mode, hipStream_t st) {
   if (b.ntiles == 0) return hipSuccess;
-  if (b.cell) {
-    if (b.nx > 4) return hipErrorInvalidValue;
+  if (b.cell)
     return b.ring ? launch_nx<true, true>(t, s, b, n_sweeps, init_mode, st)
                   : launch_nx<true, false>(t, s, b, n_sweeps, init_mode, st);
-  }
   return b.ring ? launch_nx<false, true>(t, s, b, n_sweeps, init_mode, st)
                 : launch_nx<false, false>(t, s, b, n_sweeps, init_mode, st);
 }

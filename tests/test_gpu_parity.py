@@ -140,3 +140,43 @@ def test_stats_counters():
     stats = st.host("stats")
     assert stats[3] == 10 * 256 * 16  # attempts
     assert 0 < stats[2] <= stats[1]
+
+
+@pytest.mark.parametrize("tpw,G", [(512, 1), (256, 2), (128, 3), (64, 1), (64, 4)])
+def test_parity_launch_shapes_large_template(tpw, G):
+    """Every launch shape gives the same chain (8x8 cells, S = 512)."""
+    wl = Workload("shape S=512", [make_chimera_system(8, 6, 31, 5), make_chimera_system(8, 7, 32, 3)], 0, 1)
+    say(wl.name, "tpw", tpw, "G", G)
+    g, st = make_state(wl)
+    g.set_launch(0, tpw, G)
+    chains = chains_for(wl, [0, 1])
+    for n in (1, 3):
+        st.sweep(n, 1)
+        for s, ch in enumerate(chains):
+            ch.sweeps(n, 1)
+            compare_system(st, s, ch, f"tpw={tpw} G={G}")
+
+
+@pytest.mark.parametrize("tpw,G", [(16, 4), (16, 9), (32, 8), (64, 2), (128, 1)])
+def test_parity_launch_shapes_small_template(tpw, G):
+    wl = Workload("shape S=128", [make_chimera_system(4, 9, 33, 9)], 0, 1)
+    say(wl.name, "tpw", tpw, "G", G)
+    g, st = make_state(wl)
+    g.set_launch(0, tpw, G)
+    ch = chains_for(wl, [0])[0]
+    for n in (2, 1):
+        st.sweep(n, 1)
+        ch.sweeps(n, 1)
+        compare_system(st, 0, ch, f"tpw={tpw} G={G}")
+
+
+def test_launch_shape_rejected():
+    import paper_1004_0024_amd as pa
+    wl = Workload("shape S=512", [make_chimera_system(8, 4, 31, 2)], 0, 1)
+    g, st = make_state(wl)
+    before = g.buckets()[0]
+    for tpw, G in [(32, 2), (48, 1), (1024, 2), (64, 0)]:
+        with pytest.raises(pa.IsingError) as e:
+            g.set_launch(0, tpw, G)
+        assert e.value.code == -2
+    assert g.buckets()[0] == before

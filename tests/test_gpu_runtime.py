@@ -1,0 +1,90 @@
+"""Runtime around the sweep on the GPU: captured sweep loops (HIP graphs),
+the launch-shape autotuner, checkpoint / resume.  Every chain is checked
+against the oracle bit for bit."""
+import numpy as np
+import pytest
+
+from gen import Workload, make_chimera_system
+
+from .gpu_util import chains_for, compare_system, make_state, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _small():
+    return Workload("runtime", [make_chimera_system(2, 6, 41, 6), make_chimera_system(3, 5, 42, 5)], 0, 1)
+
+
+def test_graph_replay_matches_oracle():
+    """Replays of one captured 7-sweep loop, with eager work between them."""
+    import torch
+    wl = _small()
+    say("graph replay", wl.name)
+    g, st = make_state(wl)
+    chains = chains_for(wl, [0, 1])
+    rep = st.capture(7, swap_every=1, record=True)
+    for k in range(3):
+        e = rep.launch()
+        rep.stream.synchronize()
+        recs = [ch.sweeps(7, 1, record_energy=True)["energy"] for ch in chains]
+        for s, ch in enumerate(chains):
+            compare_system(st, s, ch, f"replay {k}")
+            w0, w1 = int(g.walker_base[s]), int(g.walker_base[s + 1])
+            assert np.array_equal(e.cpu().numpy()[:, w0:w1], recs[s])
+        st.observables()  # eager work between replays
+        torch.cuda.synchronize()
+    assert st.sweeps == 21 and st.rounds == 21
+
+
+def test_graph_replay_rejects_other_phase():
+    import paper_1004_0024_amd as pa
+    wl = _small()
+    g, st = make_state(wl)
+    rep = st.capture(4, swap_every=1)
+    st.sweep(1, 1)  # now one swap round ahead of the capture
+    with pytest.raises(pa.IsingError) as e:
+        rep.launch()
+    assert e.value.code == -5
+
+
+def test_autotune_keeps_the_chain():
+    import paper_1004_0024_amd as pa
+    wl = Workload("tune", [make_chimera_system(4, 8, 51, 8), make_chimera_system(2, 8, 52, 16)], 0, 1)
+    say("autotune", wl.name)
+    g = pa.Graph(wl.systems)
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    rows = g.autotune(scratch, reps=2)
+    assert len(rows) > 4 and all(r["us_per_sweep"] > 0 for r in rows)
+    for b in g.buckets():
+        best = min((r for r in rows if r["bucket"] == g.buckets().index(b)), key=lambda r: r["us_per_sweep"])
+        assert (b["tpw"], b["G"]) == (best["tpw"], best["G"])
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    chains = chains_for(wl, [0, 1])
+    st.sweep(5, 1)
+    for s, ch in enumerate(chains):
+        ch.sweeps(5, 1)
+        compare_system(st, s, ch, "after autotune")
+
+
+def test_checkpoint_resume_bit_identical():
+    """Saving every state buffer and the two counters, then resuming, continues
+    the chain exactly as an uninterrupted run."""
+    import paper_1004_0024_amd as pa
+    wl = _small()
+    g, st = make_state(wl)
+    st.sweep(5, 2)
+    ckpt = {k: v.clone() for k, v in st.t.items()}
+    counters = (st.sweeps, st.rounds)
+    st.sweep(6, 2)
+    ref = {k: v.cpu().numpy() for k, v in st.t.items()}
+    st2 = pa.State(g)
+    for k, v in ckpt.items():
+        st2.t[k].copy_(v)
+    st2._s.sweeps, st2._s.rounds = counters
+    st2.sweep(6, 2)
+    for k, v in st2.t.items():
+        assert np.array_equal(v.cpu().numpy(), ref[k]), k
+    chains = chains_for(wl, [0, 1])
+    for s, ch in enumerate(chains):
+        ch.sweeps(11, 2)
+        compare_system(st2, s, ch, "resumed")

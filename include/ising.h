@@ -141,22 +141,27 @@ typedef struct {
   uint64_t *flips;     /* [R] accepted flips */
   uint64_t *swap_att;  /* [slots] attempts of pair (k, k+1), at slot index k */
   uint64_t *swap_acc;  /* [slots] acceptances */
-  uint64_t *stats;     /* [ISING_N_STATS] */
+  uint64_t *stats;     /* [ISING_N_STATS]: see ising_stats */
+  uint64_t *wsteps;    /* [R][2] per walker: wavefront steps with an active spin, with a flip */
   int64_t sweeps;      /* host: sweeps done (set by the library) */
   int64_t rounds;      /* host: swap rounds done */
 } ising_state;
 
 enum {
   ISING_STAT_NEAR = 0,       /* swap decisions within 1e-12 of the threshold */
-  ISING_STAT_WAVE_STEPS = 1, /* (wavefront, level) steps with an active spin */
-  ISING_STAT_WAVE_FLIP = 2,  /* of those, steps in which some lane flipped */
+  ISING_STAT_WAVE_STEPS = 1, /* wavefront steps (64 lanes, one level) with an active spin */
+  ISING_STAT_WAVE_FLIP = 2,  /* of those, steps in which some lane flipped (the analogue of
+                                the paper's probability of waiting for a flip, Section 4) */
   ISING_STAT_ATTEMPTS = 3,   /* spin-flip attempts */
+  ISING_STAT_FLIPS = 4,      /* accepted flips */
+  ISING_STAT_SWAP_ATT = 5,   /* swap attempts */
+  ISING_STAT_SWAP_ACC = 6,   /* accepted swaps */
   ISING_N_STATS = 8
 };
 
 /* Element counts: [spins, mt, energy, temp_of, walker_at, swap_mt, flips,
- * swap_att, swap_acc, stats]. */
-#define ISING_STATE_NARRAYS 10
+ * swap_att, swap_acc, stats, wsteps]. */
+#define ISING_STATE_NARRAYS 11
 int32_t ising_state_sizes(const ising_graph *g, int64_t *counts);
 
 /* Seed every walker stream (MT19937 init_genrand with walker_seeds[r]) and
@@ -190,7 +195,7 @@ void ising_replay_free(ising_replay *r);
  * of two, walkers per group 1, 2, 4 .. 32) with HIP events over `reps`
  * single-sweep launches on `scratch` (an initialised state of this graph whose
  * chain it advances), then keep the fastest shape.  Optionally writes one row
- * {bucket, tpw, walkers_per_group, microseconds per sweep} per trial to
+ * {bucket, tpw, walkers_per_group, nanoseconds per sweep} per trial to
  * report[report_rows][4].  Returns the number of rows written (>= 0) or an
  * error code.  Synchronous.                                                  */
 int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream, int64_t *report,
@@ -199,6 +204,10 @@ int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void 
 /* One swap round of every system with the given parity (0: pairs (0,1),(2,3)..;
  * 1: (1,2),(3,4)..).  Does not change st->rounds.                             */
 int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream);
+
+/* Totals over all walkers into host out[ISING_N_STATS] (reduces the per-walker
+ * counters on the device; synchronises `stream`).                           */
+int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, void *stream);
 
 /* Observables per walker into device int32 obs[R][4]: cost recomputed from the
  * spins, magnetisation sum_i s_i, running cost, temperature slot.            */

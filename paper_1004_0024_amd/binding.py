@@ -33,7 +33,7 @@ class StateStruct(C.Structure):
     _fields_ = [
         ("spins", C.c_void_p), ("mt", C.c_void_p), ("energy", C.c_void_p), ("temp_of", C.c_void_p),
         ("walker_at", C.c_void_p), ("swap_mt", C.c_void_p), ("flips", C.c_void_p),
-        ("swap_att", C.c_void_p), ("swap_acc", C.c_void_p), ("stats", C.c_void_p),
+        ("swap_att", C.c_void_p), ("swap_acc", C.c_void_p), ("stats", C.c_void_p), ("wsteps", C.c_void_p),
         ("sweeps", C.c_int64), ("rounds", C.c_int64),
     ]
 
@@ -64,6 +64,7 @@ def lib():
             "ising_sweep": ([P, P, i32, i32, P, P], i32),
             "pt_swap": ([P, P, i32, P], i32),
             "ising_observables": ([P, P, P, P], i32),
+            "ising_stats": ([P, P, P, P], i32),
             "ising_threshold_row": ([C.c_double, i32, P], i32),
             "ising_level_offsets": ([P, P, P], i32),
             "ising_last_error": ([], C.c_char_p),
@@ -183,24 +184,24 @@ class Graph:
         n = lib().ising_autotune(self._handle, C.byref(scratch_state._s), int(reps), _stream(), _np_ptr(rep), rows)
         if n < 0:
             _check(n)
-        return [dict(bucket=int(r[0]), tpw=int(r[1]), G=int(r[2]), us_per_sweep=int(r[3])) for r in rep[:n]]
+        return [dict(bucket=int(r[0]), tpw=int(r[1]), G=int(r[2]), ns_per_sweep=int(r[3])) for r in rep[:n]]
 
 
 class State:
     """Chain state in torch device tensors, walker-major."""
 
     _FIELDS = ["spins", "mt", "energy", "temp_of", "walker_at", "swap_mt", "flips", "swap_att", "swap_acc",
-               "stats"]
+               "stats", "wsteps"]
 
     def __init__(self, graph: Graph):
         import torch
         self.graph = graph
-        counts = np.zeros(10, np.int64)
+        counts = np.zeros(11, np.int64)
         _check(lib().ising_state_sizes(graph.handle, _np_ptr(counts)))
         dev = graph.tables.device
         dt = {"spins": torch.int32, "mt": torch.int32, "energy": torch.int32, "temp_of": torch.int32,
               "walker_at": torch.int32, "swap_mt": torch.int32, "flips": torch.int64, "swap_att": torch.int64,
-              "swap_acc": torch.int64, "stats": torch.int64}
+              "swap_acc": torch.int64, "stats": torch.int64, "wsteps": torch.int64}
         self.t = {}
         for name, n in zip(self._FIELDS, counts):
             self.t[name] = torch.zeros(max(int(n), 1), dtype=dt[name], device=dev)
@@ -236,6 +237,14 @@ class State:
 
     def swap(self, parity):
         _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))
+
+    def stats(self):
+        """Totals: near-threshold swaps, wavefront steps, steps with a flip, attempts,
+        flips, swap attempts, accepted swaps."""
+        out = np.zeros(ISING_N_STATS, np.uint64)
+        _check(lib().ising_stats(self.graph.handle, C.byref(self._s), _np_ptr(out), _stream()))
+        keys = ["near", "wave_steps", "wave_flip_steps", "attempts", "flips", "swap_att", "swap_acc"]
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def observables(self):
         import torch

@@ -508,19 +508,20 @@ extern "C" int32_t ising_state_sizes(const ising_graph *g, int64_t *c) {
   c[7] = g->slots;
   c[8] = g->slots;
   c[9] = ISING_N_STATS;
+  c[10] = 2 * g->R;
   return ISING_OK;
 }
 
 static int32_t check_state(const ising_state *st) {
   if (!st || !st->spins || !st->mt || !st->energy || !st->temp_of || !st->walker_at || !st->swap_mt ||
-      !st->flips || !st->swap_att || !st->swap_acc || !st->stats)
+      !st->flips || !st->swap_att || !st->swap_acc || !st->stats || !st->wsteps)
     return fail(ISING_E_INVAL, "state has a NULL buffer");
   return ISING_OK;
 }
 
 static DevState dev_state(const ising_state *st) {
   return DevState{st->spins, st->mt, st->energy, st->temp_of, st->walker_at, st->swap_mt,
-                  st->flips, st->swap_att, st->swap_acc, st->stats};
+                  st->flips, st->swap_att, st->swap_acc, st->stats, st->wsteps};
 }
 
 extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *walker_seeds,
@@ -543,6 +544,7 @@ extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const
   HIP_TRY(hipMemsetAsync(st->swap_att, 0, sizeof(uint64_t) * g->slots, s), "init_state clear");
   HIP_TRY(hipMemsetAsync(st->swap_acc, 0, sizeof(uint64_t) * g->slots, s), "init_state clear");
   HIP_TRY(hipMemsetAsync(st->stats, 0, sizeof(uint64_t) * ISING_N_STATS, s), "init_state clear");
+  HIP_TRY(hipMemsetAsync(st->wsteps, 0, sizeof(uint64_t) * 2 * g->R, s), "init_state clear");
   HIP_TRY(launch_labels(g->dev, d, (int32_t)g->R, g->n_sys, s), "labels kernel");
   for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, 0, 1, s), "initial spins");
   HIP_TRY(launch_observables(g->dev, d, (int32_t)g->R, nullptr, 1, s), "initial energies");
@@ -681,7 +683,7 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
     for (int32_t sy : g->bucket_sys[bi]) Kmax = std::max(Kmax, g->sys[sy].K);
     const Bucket orig = g->buckets[bi];
     Bucket best = orig;
-    float best_ms = -1.f;
+    int64_t best_ns = -1;
     for (int32_t tpw = 8; tpw <= 1024; tpw <<= 1) {
       for (int32_t G = 1; G <= 32; G <<= 1) {
         Bucket b = orig;
@@ -699,17 +701,17 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
         HIP_TRY(hipEventSynchronize(e1), "autotune sync");
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "autotune time");
-        ms /= (float)reps;
+        const int64_t ns = (int64_t)((double)ms * 1e6 / reps);  // per sweep
         if (report && row < report_rows) {
           int64_t *o = report + (size_t)row * 4;
           o[0] = (int64_t)bi;
           o[1] = tpw;
           o[2] = G;
-          o[3] = (int64_t)(ms * 1000.f);  // microseconds per sweep
+          o[3] = ns;
           ++row;
         }
-        if (best_ms < 0.f || ms < best_ms) {
-          best_ms = ms;
+        if (best_ns < 0 || ns < best_ns) {
+          best_ns = ns;
           best = g->buckets[bi];
         }
       }
@@ -725,6 +727,18 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
           "autotune tiles");
   HIP_TRY(hipStreamSynchronize(s), "autotune sync");
   return row;
+}
+
+extern "C" int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, void *stream) {
+  if (!g || !out) return fail(ISING_E_INVAL, "stats: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_reduce_stats(dev_state(st), (int32_t)g->R, (int32_t)g->slots, s), "stats kernel");
+  HIP_TRY(hipMemcpyAsync(out, st->stats, sizeof(uint64_t) * ISING_N_STATS, hipMemcpyDeviceToHost, s), "stats copy");
+  HIP_TRY(hipStreamSynchronize(s), "stats sync");
+  out[ISING_STAT_ATTEMPTS] = (uint64_t)(st->sweeps > 0 ? st->sweeps : 0) * (uint64_t)g->attempts;
+  return ISING_OK;
 }
 
 extern "C" int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream) {

@@ -24,6 +24,42 @@ hipError_t launch_seed(const DevState &s, int32_t R, int32_t n_sys, hipStream_t 
   return hipGetLastError();
 }
 
+// ---- totals of the per-walker and per-pair counters -----------------------
+// stats[1..2] wavefront steps, [4] flips, [5..6] swap attempts / acceptances;
+// one workgroup, fixed-order tree reductions (no atomics).
+__global__ void __launch_bounds__(256) reduce_stats_kernel(DevState St, int32_t R, int32_t slots) {
+  __shared__ unsigned long long red[5][256];
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    v[0] += St.wsteps[2 * (size_t)r];
+    v[1] += St.wsteps[2 * (size_t)r + 1];
+    v[2] += St.flips[r];
+  }
+  for (int k = threadIdx.x; k < slots; k += blockDim.x) {
+    v[3] += St.swap_att[k];
+    v[4] += St.swap_acc[k];
+  }
+  for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = v[i];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    St.stats[1] = red[0][0];
+    St.stats[2] = red[1][0];
+    St.stats[4] = red[2][0];
+    St.stats[5] = red[3][0];
+    St.stats[6] = red[4][0];
+  }
+}
+
+hipError_t launch_reduce_stats(const DevState &s, int32_t R, int32_t slots, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_stats_kernel, dim3(1), dim3(256), 0, st, s, R, slots);
+  return hipGetLastError();
+}
+
 // ---- labels: walker j of a system at slot j -------------------------------
 __global__ void labels_kernel(DevTables T, DevState St, int32_t R) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;

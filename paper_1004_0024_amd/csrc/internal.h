@@ -89,7 +89,7 @@ struct DevState {
   uint32_t *spins, *mt;
   int32_t *energy, *temp_of, *walker_at;
   uint32_t *swap_mt;
-  uint64_t *flips, *swap_att, *swap_acc, *stats;
+  uint64_t *flips, *swap_att, *swap_acc, *stats, *wsteps;
 };
 
 // Kernel launchers (each returns the hipError_t of the launch).
@@ -104,6 +104,7 @@ hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, i
                          hipStream_t st);
 hipError_t launch_observables(const DevTables &t, const DevState &s, int32_t R, int32_t *obs,
                               int32_t set_energy, hipStream_t st);
+hipError_t launch_reduce_stats(const DevState &s, int32_t R, int32_t slots, hipStream_t st);
 hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32_t n_sys,
                          hipStream_t st);
 

@@ -273,12 +273,11 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   if (live && !init_mode) {
     atomicAdd(&acc[0], dE);
     atomicAdd(&acc[1], nfl);
-  }
-  if (!init_mode && (tid & 63) == 0) {
-    atomicAdd((unsigned long long *)&St.stats[1], (unsigned long long)st_steps);
-    atomicAdd((unsigned long long *)&St.stats[2], (unsigned long long)st_flip);
-    if (tid == 0)
-      atomicAdd((unsigned long long *)&St.stats[3], (unsigned long long)nw * S * M * n_sweeps);
+    // wavefront statistics go to the walker of the wavefront's first lane
+    if ((tid & 63) == 0) {
+      atomicAdd(&acc[2], (int)st_steps);
+      atomicAdd(&acc[3], (int)st_flip);
+    }
   }
   __syncthreads();
   for (int i = tid; i < nw * WW; i += nthr) {
@@ -296,6 +295,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + WW + kThrRow);
     St.energy[r] += a[0];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
+    St.wsteps[2 * (size_t)r] += (unsigned long long)(uint32_t)a[2];
+    St.wsteps[2 * (size_t)r + 1] += (unsigned long long)(uint32_t)a[3];
   }
 }
 

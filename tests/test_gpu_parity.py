@@ -137,9 +137,15 @@ def test_stats_counters():
     wl = make_workload("A")
     g, st = make_state(wl)
     st.sweep(10, 1)
-    stats = st.host("stats")
-    assert stats[3] == 10 * 256 * 16  # attempts
-    assert 0 < stats[2] <= stats[1]
+    stats = st.stats()
+    assert stats["attempts"] == 10 * 256 * 16
+    assert 0 < stats["wave_flip_steps"] <= stats["wave_steps"]
+    assert stats["flips"] == int(st.host("flips").sum())
+    ch = chains_for(wl, [0])[0]
+    ch.sweeps(10, 1)
+    c = ch.counters()
+    assert stats["flips"] == int(c["flips"].sum())
+    assert stats["swap_att"] == int(c["swap_att"].sum()) and stats["swap_acc"] == int(c["swap_acc"].sum())
 
 
 @pytest.mark.parametrize("tpw,G", [(512, 1), (256, 2), (128, 3), (64, 1), (64, 4)])

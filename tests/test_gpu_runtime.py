@@ -16,24 +16,25 @@ def _small():
 
 
 def test_graph_replay_matches_oracle():
-    """Replays of one captured 7-sweep loop, with eager work between them."""
+    """Replays of one captured 8-sweep loop (an even number of swap rounds, so
+    every replay starts in the captured phase), with eager work between them."""
     import torch
     wl = _small()
     say("graph replay", wl.name)
     g, st = make_state(wl)
     chains = chains_for(wl, [0, 1])
-    rep = st.capture(7, swap_every=1, record=True)
+    rep = st.capture(8, swap_every=1, record=True)
     for k in range(3):
         e = rep.launch()
         rep.stream.synchronize()
-        recs = [ch.sweeps(7, 1, record_energy=True)["energy"] for ch in chains]
+        recs = [ch.sweeps(8, 1, record_energy=True)["energy"] for ch in chains]
         for s, ch in enumerate(chains):
             compare_system(st, s, ch, f"replay {k}")
             w0, w1 = int(g.walker_base[s]), int(g.walker_base[s + 1])
             assert np.array_equal(e.cpu().numpy()[:, w0:w1], recs[s])
         st.observables()  # eager work between replays
         torch.cuda.synchronize()
-    assert st.sweeps == 21 and st.rounds == 21
+    assert st.sweeps == 24 and st.rounds == 24
 
 
 def test_graph_replay_rejects_other_phase():
@@ -45,6 +46,11 @@ def test_graph_replay_rejects_other_phase():
     with pytest.raises(pa.IsingError) as e:
         rep.launch()
     assert e.value.code == -5
+    odd = st.capture(3, swap_every=1)  # an odd number of rounds flips the phase
+    odd.launch()
+    odd.stream.synchronize()
+    with pytest.raises(pa.IsingError):
+        odd.launch()
 
 
 def test_autotune_keeps_the_chain():
@@ -54,9 +60,9 @@ def test_autotune_keeps_the_chain():
     g = pa.Graph(wl.systems)
     scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
     rows = g.autotune(scratch, reps=2)
-    assert len(rows) > 4 and all(r["us_per_sweep"] > 0 for r in rows)
-    for b in g.buckets():
-        best = min((r for r in rows if r["bucket"] == g.buckets().index(b)), key=lambda r: r["us_per_sweep"])
+    assert len(rows) > 4 and all(r["ns_per_sweep"] > 0 for r in rows)
+    for bi, b in enumerate(g.buckets()):
+        best = min((r for r in rows if r["bucket"] == bi), key=lambda r: r["ns_per_sweep"])
         assert (b["tpw"], b["G"]) == (best["tpw"], best["G"])
     st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
     chains = chains_for(wl, [0, 1])

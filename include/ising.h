@@ -213,6 +213,40 @@ int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, 
  * spins, magnetisation sum_i s_i, running cost, temperature slot.            */
 int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *obs, void *stream);
 
+/* ---- learned cell proposal --------------------------------------------------
+ * An extension of the method (the paper has no learned part): a unit cell of
+ * 8 spins of one slice is re-proposed jointly by a 17 -> 128 -> 128 -> 8 ReLU
+ * network q(s'|b, beta) given its boundary fields b_k = h_k + sum over
+ * neighbours j outside the cell of J_kj s_j, with input
+ * [0 x 8, b/8, beta]; outputs are 8 independent Bernoulli logits (spin +1).
+ * Moves are accepted with the exact Metropolis-Hastings probability
+ * min(1, exp(-beta dE) q(s)/q(s')), dE the integer change of the cost
+ * function, so the target distribution is unchanged.  Products run on BF16
+ * matrix cores with FP32 sums; the parameters are FP32.
+ * Parameter layout (ISING_MLP_PARAMS floats): W1[128][17], b1[128],
+ * W2[128][128], b2[128], W3[8][128], b3[8].                                   */
+#define ISING_MLP_PARAMS 19848
+#define ISING_MLP_PACKED 43008 /* uint16 words of the packed BF16 copies */
+typedef struct {
+  float *w;       /* [ISING_MLP_PARAMS] FP32 master weights (device) */
+  float *m, *v;   /* [ISING_MLP_PARAMS] Adam moments (device) */
+  float *grad;    /* [ISING_MLP_PARAMS] gradient (device, written by ising_mlp_grad) */
+  uint16_t *wb;   /* [ISING_MLP_PACKED] BF16 copies read by the kernels (device) */
+  int64_t step;   /* host: Adam steps done */
+} ising_mlp;
+
+/* Refresh net->wb from net->w (after the caller writes w). */
+int32_t ising_mlp_pack(ising_mlp *net, void *stream);
+/* logits[n][8] (device) of inputs x[n][17] (device FP32). */
+int32_t ising_mlp_forward(const ising_mlp *net, const float *x, int32_t n, float *logits, void *stream);
+/* net->grad = gradient of mean_r -log q(y_r | x_r), y[r] (device bytes) bit k
+ * set when cell spin k is +1; *loss (device, nullable) = that mean.  One
+ * workgroup, deterministic. */
+int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n, float *loss,
+                       void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with net->grad, then repack. */
+int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream);
+
 /* ---- host-only helpers (no device work; usable without a GPU) ------------ */
 
 /* thr[d] = ceil(2^32 * exp(-2.0 * beta * d)) - 1 for d = 1..dmax, thr[0] =

@@ -12,6 +12,8 @@ from .binding import (  # noqa: F401
     STAT_WAVE_FLIP,
     STAT_WAVE_STEPS,
     IsingError,
+    Mlp,
+    Replay,
     Graph,
     State,
     lib,

@@ -75,6 +75,10 @@ def lib():
             "ising_replay_launch": ([P, P, P], i32),
             "ising_replay_free": ([P], None),
             "ising_autotune": ([P, P, i32, P, P, i32], i32),
+            "ising_mlp_pack": ([P, P], i32),
+            "ising_mlp_forward": ([P, P, i32, P, P], i32),
+            "ising_mlp_grad": ([P, P, P, i32, P, P], i32),
+            "ising_mlp_adam": ([P, C.c_float, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -305,3 +309,53 @@ class Replay:
         if h and _lib is not None:
             _lib.ising_replay_free(h)
             self._h = None
+
+
+class MlpStruct(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("grad", C.c_void_p),
+                ("wb", C.c_void_p), ("step", C.c_int64)]
+
+
+MLP_PARAMS, MLP_PACKED = 19848, 43008
+
+
+class Mlp:
+    """Network of the learned cell proposal: FP32 master weights, Adam moments, BF16 copies."""
+
+    def __init__(self, params, device="cuda"):
+        import torch
+        p = torch.as_tensor(np.asarray(params, np.float32)).to(device)
+        assert p.numel() == MLP_PARAMS
+        self.w = p.contiguous()
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.grad = torch.zeros_like(self.w)
+        self.wb = torch.zeros(MLP_PACKED, dtype=torch.int16, device=device)
+        self._s = MlpStruct(self.w.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.grad.data_ptr(),
+                            self.wb.data_ptr(), 0)
+        _check(lib().ising_mlp_pack(C.byref(self._s), _stream()))
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous().float()
+        out = torch.empty((x.shape[0], 8), dtype=torch.float32, device=x.device)
+        _check(lib().ising_mlp_forward(C.byref(self._s), C.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                       C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def grad_step(self, x, y):
+        """Writes self.grad; returns the mean loss (device scalar)."""
+        import torch
+        x = x.contiguous().float()
+        y = y.contiguous().to(torch.uint8)
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        _check(lib().ising_mlp_grad(C.byref(self._s), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                    int(x.shape[0]), C.c_void_p(loss.data_ptr()), _stream()))
+        return loss
+
+    def adam(self, lr):
+        _check(lib().ising_mlp_adam(C.byref(self._s), C.c_float(lr), _stream()))
+
+    @property
+    def steps(self):
+        return int(self._s.step)

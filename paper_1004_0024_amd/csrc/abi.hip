@@ -14,6 +14,7 @@
 
 #include "../../include/ising.h"
 #include "internal.h"
+#include "mlp.h"
 
 using namespace ising;
 
@@ -756,5 +757,51 @@ extern "C" int32_t ising_observables(const ising_graph *g, const ising_state *st
   if (rc) return rc;
   HIP_TRY(launch_observables(g->dev, dev_state(st), (int32_t)g->R, obs, 0, (hipStream_t)stream),
           "observables kernel");
+  return ISING_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned cell proposal: network entry points
+// ---------------------------------------------------------------------------
+static int32_t check_mlp(const ising_mlp *net) {
+  if (!net || !net->w || !net->m || !net->v || !net->grad || !net->wb)
+    return fail(ISING_E_INVAL, "mlp: NULL buffer");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_mlp_pack(ising_mlp *net, void *stream) {
+  int32_t rc = check_mlp(net);
+  if (rc) return rc;
+  HIP_TRY(launch_mlp_pack(net->w, net->wb, (hipStream_t)stream), "mlp pack");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_mlp_forward(const ising_mlp *net, const float *x, int32_t n, float *logits,
+                                     void *stream) {
+  int32_t rc = check_mlp(net);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!x || !logits))) return fail(ISING_E_INVAL, "mlp_forward: bad arguments");
+  HIP_TRY(launch_mlp_forward(net->w, net->wb, x, n, logits, (hipStream_t)stream), "mlp forward");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n,
+                                  float *loss, void *stream) {
+  int32_t rc = check_mlp(net);
+  if (rc) return rc;
+  if (n < 1 || !x || !y) return fail(ISING_E_INVAL, "mlp_grad: bad arguments");
+  HIP_TRY(launch_mlp_grad(net->w, net->wb, x, y, n, net->grad, loss, (hipStream_t)stream), "mlp grad");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream) {
+  int32_t rc = check_mlp(net);
+  if (rc) return rc;
+  if (!(lr > 0.f)) return fail(ISING_E_INVAL, "mlp_adam: lr must be > 0");
+  net->step += 1;
+  HIP_TRY(launch_adam(net->w, net->m, net->v, net->grad, kNParams, lr, 0.9f, 0.999f, 1e-8f, net->step,
+                      (hipStream_t)stream),
+          "adam");
+  HIP_TRY(launch_mlp_pack(net->w, net->wb, (hipStream_t)stream), "mlp pack");
   return ISING_OK;
 }

@@ -247,6 +247,29 @@ int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const uint8_t *y, i
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with net->grad, then repack. */
 int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream);
 
+/* Cells: systems whose template is a grid of L x L 8-spin cells (spins
+ * (y*L + x)*8 + 0..7 of a slice form cell (y, x), every spin joined to the 4
+ * spins of the other half of its cell, and in-slice edges between cells only
+ * join grid neighbours).  Cell (m, y, x) of a walker has index (m*L + y)*L + x.
+ * Other systems are left out of cell moves.
+ *
+ * Training rows: row i is cell number (offset + i*stride) mod (all cells of
+ * all walkers, walker-major): x[i][17] (device FP32) its network input, y[i]
+ * its 8 spins (bit k set when spin k is +1).                                  */
+int32_t ising_collect_cells(const ising_graph *g, const ising_state *st, int64_t stride, int64_t offset,
+                            int32_t n, float *x, uint8_t *y, void *stream);
+/* One pass of cell moves over every walker: the colour classes of cells in
+ * order (cells of one class share no edge and move at once); each cell gets a
+ * joint proposal from the network and the Metropolis-Hastings test.  Uniforms:
+ * Philox4x64-10 with key (key, walker), counters (pass_index, cell, 0, 0) and
+ * (pass_index, cell, 1, 0): high halves of the eight words are the proposal
+ * uniforms, the low half of the first word the acceptance uniform.  Energies
+ * are kept exact.  `work` (device, caller-owned) holds ising_propose_bytes
+ * bytes; moves (device, nullable) [R][2] += proposals, acceptances.          */
+int32_t ising_propose_bytes(const ising_graph *g, size_t *bytes);
+int32_t ising_propose_cells(const ising_graph *g, ising_state *st, const ising_mlp *net, uint64_t key,
+                            int64_t pass_index, void *work, size_t work_bytes, uint64_t *moves, void *stream);
+
 /* ---- host-only helpers (no device work; usable without a GPU) ------------ */
 
 /* thr[d] = ceil(2^32 * exp(-2.0 * beta * d)) - 1 for d = 1..dmax, thr[0] =

@@ -220,13 +220,14 @@ class CellModel:
         return e
 
 
-def learned_pass(model, spins, energy, betas, params, key_base, walker_ids, pass_index):
+def learned_pass(model, spins, energy, betas, params, key_base, walker_ids, pass_index, forward_fn=None):
     """One pass of cell proposals over every walker of one system (FP64).
 
     spins [K, N] (+-1, modified in place), energy [K] (modified), betas [K] (each
     walker's current inverse temperature).  Colours in order; inside a colour the
     cells are independent.  Returns accepted moves per walker."""
     p = unpack(params) if not isinstance(params, dict) else params
+    fwd = forward if forward_fn is None else forward_fn
     sysm = model.system
     L = sysm.L
     acc = np.zeros(len(spins), np.int64)
@@ -239,7 +240,7 @@ def learned_pass(model, spins, energy, betas, params, key_base, walker_ids, pass
                     continue
                 idx = model.cell_spins(m, y, x)
                 b = model.boundary(s, idx)
-                logits, _ = forward(p, features(b[None, :], [beta]))
+                logits, _ = fwd(p, features(b[None, :], [beta]))
                 logits = logits[0]
                 u = cell_uniforms(key_base, walker_ids[w], pass_index, ci)
                 prob = 1.0 / (1.0 + np.exp(-logits))

@@ -61,6 +61,9 @@ extern "C" int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr)
 
 struct SysHost {
   int32_t S, M, ring, F, deg, dmax, K, cell, FW;
+  int32_t grid_L = 0, n_phases = 0;
+  std::vector<uint16_t> cells;  // cell indices, phase by phase
+  int32_t pc[5] = {0, 0, 0, 0, 0};
   std::vector<TmplSpin> tmpl;
   std::vector<uint32_t> fifo;  // (queue base << 8) | log2(depth) per template spin
   std::vector<double> beta;
@@ -181,6 +184,39 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
     fw += dq;
   }
   out.FW = fw;
+  // Grid of 8-spin cells (cell moves): S = 8 L^2, cell templates, and every
+  // in-slice edge between two cells joins grid neighbours; then cells coloured
+  // (y + x + m) mod 2 share no edge (on a ring of odd length the last slice
+  // takes colours 2 and 3).
+  out.grid_L = 0;
+  if (cell) {
+    int32_t L = 1;
+    while (8 * L * L < S) ++L;
+    bool grid = 8 * L * L == S && (int64_t)L * L * M <= 65535;
+    for (int32_t e = 0; e < d.n_edges && grid; ++e) {
+      const int32_t ca = d.edge_u[e] / 8, cb = d.edge_v[e] / 8;
+      if (ca == cb) continue;
+      const int32_t dy = std::abs(ca / L - cb / L), dx = std::abs(ca % L - cb % L);
+      grid = dy + dx == 1;
+    }
+    if (grid) {
+      out.grid_L = L;
+      out.n_phases = (d.ring && M % 2 == 1) ? 4 : 2;
+      std::vector<std::vector<uint16_t>> ph(out.n_phases);
+      for (int32_t m = 0; m < M; ++m)
+        for (int32_t y = 0; y < L; ++y)
+          for (int32_t x = 0; x < L; ++x) {
+            const int32_t col = (d.ring && M % 2 == 1 && m == M - 1) ? 2 + (y + x) % 2 : (y + x + m) % 2;
+            ph[col].push_back((uint16_t)((m * L + y) * L + x));
+          }
+      out.cells.clear();
+      for (int32_t p = 0; p < out.n_phases; ++p) {
+        out.pc[p] = (int32_t)out.cells.size();
+        out.cells.insert(out.cells.end(), ph[p].begin(), ph[p].end());
+      }
+      for (int32_t p = out.n_phases; p < 5; ++p) out.pc[p] = (int32_t)out.cells.size();
+    }
+  }
   out.beta.assign(d.beta, d.beta + d.n_temps);
   return ISING_OK;
 }
@@ -201,6 +237,8 @@ extern "C" int32_t ising_level_offsets(const ising_system_desc *sys, int32_t *f,
 struct ising_graph {
   int32_t n_sys = 0;
   int64_t R = 0, slots = 0, spin_words = 0, attempts = 0, max_levels = 0;
+  int64_t cell_rows = 0, total_cells = 0;
+  int32_t max_phases = 0;
   std::vector<SysInfo> sys;
   std::vector<Tile> tiles;
   std::vector<Bucket> buckets;
@@ -213,12 +251,12 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, total;
+  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, total;
 };
 
 // Device tables.  Room for one tile per walker, so any launch shape can be
 // installed later without reallocating.
-static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R) {
+static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R, int64_t n_cells) {
   Layout L{};
   size_t o = 0;
   n_tiles = std::max(n_tiles, R);
@@ -236,6 +274,8 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   o = align256(o + sizeof(Tile) * n_tiles);
   L.wsys = o;
   o = align256(o + sizeof(int32_t) * R);
+  L.cells = o;
+  o = align256(o + sizeof(uint16_t) * std::max<int64_t>(n_cells, 1));
   L.total = o;
   return L;
 }
@@ -282,7 +322,7 @@ static void tile_bucket(ising_graph &g, Bucket &b, const std::vector<int32_t> &s
 static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
   g.n_sys = (int32_t)hs.size();
   g.sys.resize(hs.size());
-  int64_t walker = 0, slot = 0, word = 0, tmpl = 0;
+  int64_t walker = 0, slot = 0, word = 0, tmpl = 0, cl = 0;
   for (size_t s = 0; s < hs.size(); ++s) {
     const SysHost &h = hs[s];
     SysInfo &si = g.sys[s];
@@ -303,6 +343,18 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.cell = h.cell;
     si.nx = h.deg - (h.cell ? 4 : 0);
     si.fifo_words = h.FW;
+    si.grid_L = h.grid_L;
+    si.n_phases = h.n_phases;
+    si.cl0 = (int32_t)cl;
+    for (int p = 0; p < 5; ++p) si.pc[p] = h.pc[p];
+    si.rows = 0;
+    for (int p = 0; p < h.n_phases; ++p) si.rows = std::max(si.rows, h.pc[p + 1] - h.pc[p]);
+    si.row0 = g.cell_rows;
+    si.cell0 = g.total_cells;
+    g.cell_rows += (int64_t)si.rows * h.K;
+    g.total_cells += h.grid_L ? (int64_t)h.grid_L * h.grid_L * h.M * h.K : 0;
+    g.max_phases = std::max(g.max_phases, h.n_phases);
+    cl += (int64_t)h.cells.size();
     walker += h.K;
     slot += h.K;
     word += (int64_t)si.WW * h.K;
@@ -364,9 +416,12 @@ extern "C" int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys
   ising_graph g;
   rc = plan(hs, g);
   if (rc) return rc;
-  int64_t ntm = 0;
-  for (auto &h : hs) ntm += h.S;
-  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R).total;
+  int64_t ntm = 0, ncl = 0;
+  for (auto &h : hs) {
+    ntm += h.S;
+    ncl += (int64_t)h.cells.size();
+  }
+  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl).total;
   return ISING_OK;
 }
 
@@ -384,9 +439,12 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
     delete g;
     return rc;
   }
-  int64_t ntm = 0;
-  for (auto &h : hs) ntm += h.S;
-  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R);
+  int64_t ntm = 0, ncl = 0;
+  for (auto &h : hs) {
+    ntm += h.S;
+    ncl += (int64_t)h.cells.size();
+  }
+  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl);
   if (bytes < L.total) {
     delete g;
     return fail(ISING_E_SIZE, "dev_tables has %zu bytes, needs %zu", bytes, L.total);
@@ -419,6 +477,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
       fo += h.S;
     }
   }
+  {
+    uint16_t *co = (uint16_t *)(host.data() + L.cells);
+    for (auto &h : hs) {
+      memcpy(co, h.cells.data(), sizeof(uint16_t) * h.cells.size());
+      co += h.cells.size();
+    }
+  }
   memcpy(host.data() + L.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size());
   memcpy(host.data() + L.wsys, g->walker_sys.data(), sizeof(int32_t) * g->walker_sys.size());
   hipStream_t st = (hipStream_t)stream;
@@ -436,6 +501,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.tiles = (const Tile *)(base + L.tiles);
   g->dev.walker_sys = (const int32_t *)(base + L.wsys);
   g->dev.fifo = (const uint32_t *)(base + L.fifo);
+  g->dev.cells = (const uint16_t *)(base + L.cells);
   g->bytes = L.total;
   *out = g;
   return ISING_OK;
@@ -803,5 +869,71 @@ extern "C" int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream) {
                       (hipStream_t)stream),
           "adam");
   HIP_TRY(launch_mlp_pack(net->w, net->wb, (hipStream_t)stream), "mlp pack");
+  return ISING_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned cell proposal: cells of the chain
+// ---------------------------------------------------------------------------
+struct ProposeWork {
+  size_t x, logits, b, total;
+};
+
+static ProposeWork propose_layout(int64_t rows) {
+  ProposeWork w{};
+  size_t o = 0;
+  w.x = o;
+  o = align256(o + sizeof(float) * kIn * rows);
+  w.logits = o;
+  o = align256(o + sizeof(float) * kOut * rows);
+  w.b = o;
+  o = align256(o + 8 * rows);
+  w.total = o;
+  return w;
+}
+
+extern "C" int32_t ising_propose_bytes(const ising_graph *g, size_t *bytes) {
+  if (!g || !bytes) return fail(ISING_E_INVAL, "propose_bytes: NULL argument");
+  if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  *bytes = propose_layout(g->cell_rows).total;
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_propose_cells(const ising_graph *g, ising_state *st, const ising_mlp *net, uint64_t key,
+                                       int64_t pass_index, void *work, size_t work_bytes, uint64_t *moves,
+                                       void *stream) {
+  if (!g || !work) return fail(ISING_E_INVAL, "propose_cells: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  rc = check_mlp(net);
+  if (rc) return rc;
+  if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  const ProposeWork lay = propose_layout(g->cell_rows);
+  if (work_bytes < lay.total) return fail(ISING_E_SIZE, "propose work has %zu bytes, needs %zu", work_bytes, lay.total);
+  if (g->cell_rows > INT32_MAX) return fail(ISING_E_RANGE, "too many cells for one pass");
+  hipStream_t s = (hipStream_t)stream;
+  DevState d = dev_state(st);
+  uint8_t *base = (uint8_t *)work;
+  float *x = (float *)(base + lay.x);
+  float *logits = (float *)(base + lay.logits);
+  int8_t *b = (int8_t *)(base + lay.b);
+  for (int32_t p = 0; p < g->max_phases; ++p) {
+    HIP_TRY(launch_cell_features(g->dev, d, g->n_sys, g->cell_rows, p, x, b, s), "cell features");
+    HIP_TRY(launch_mlp_forward(net->w, net->wb, x, (int32_t)g->cell_rows, logits, s), "cell proposals");
+    HIP_TRY(launch_cell_accept(g->dev, d, g->n_sys, g->cell_rows, p, logits, b, key, pass_index, moves, s),
+            "cell acceptance");
+  }
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_collect_cells(const ising_graph *g, const ising_state *st, int64_t stride,
+                                       int64_t offset, int32_t n, float *x, uint8_t *y, void *stream) {
+  if (!g || !x || !y || n < 0 || stride < 1 || offset < 0) return fail(ISING_E_INVAL, "collect_cells: bad arguments");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  if (g->total_cells == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  HIP_TRY(launch_collect_cells(g->dev, dev_state(st), g->n_sys, stride, offset, g->total_cells, n, x, y,
+                               (hipStream_t)stream),
+          "collect cells");
   return ISING_OK;
 }

@@ -25,6 +25,15 @@ struct SysInfo {
   int32_t nx;              // neighbours handled one by one (deg, or deg - 4 for cell templates)
   int32_t fifo_words;      // per walker: sum over template spins of their uniform-queue depths
   int32_t pad;
+  // cell moves (learned proposal); grid_L = 0 when the template is not a grid of 8-spin cells
+  int32_t grid_L;          // cells per grid side: cell (m, y, x) = spins m*S + (y*L + x)*8 + 0..7
+  int32_t n_phases;        // colour classes of cells (2, or 4 on a ring of odd length)
+  int32_t cl0;             // first entry of this system's cell list
+  int32_t pc[5];           // phase p owns cell-list entries [pc[p], pc[p+1])
+  int32_t rows;            // proposal work rows per walker (largest phase)
+  int32_t pad2;
+  int64_t row0;            // first proposal work row of walker 0
+  int64_t cell0;           // global index of walker 0's cell 0 (cells numbered walker-major)
 };
 
 // Template spin q: in-slice neighbours with their couplings, field, tau coupling,
@@ -83,6 +92,7 @@ struct DevTables {
   const Tile *tiles;
   const int32_t *walker_sys;  // [R] system of each walker
   const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
+  const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
 };
 
 struct DevState {
@@ -104,6 +114,14 @@ hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, i
                          hipStream_t st);
 hipError_t launch_observables(const DevTables &t, const DevState &s, int32_t R, int32_t *obs,
                               int32_t set_energy, hipStream_t st);
+hipError_t launch_cell_features(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
+                                int32_t phase, float *x, int8_t *b, hipStream_t st);
+hipError_t launch_cell_accept(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total, int32_t phase,
+                              const float *logits, const int8_t *b, uint64_t key, int64_t pass_index,
+                              uint64_t *moves, hipStream_t st);
+hipError_t launch_collect_cells(const DevTables &t, const DevState &s, int32_t n_sys, int64_t stride,
+                                int64_t offset, int64_t total_cells, int32_t n, float *x, uint8_t *y,
+                                hipStream_t st);
 hipError_t launch_reduce_stats(const DevState &s, int32_t R, int32_t slots, hipStream_t st);
 hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32_t n_sys,
                          hipStream_t st);

@@ -205,6 +205,9 @@ int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void 
  * 1: (1,2),(3,4)..).  Does not change st->rounds.                             */
 int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream);
 
+/* e_row[slots] (device) = running energy of the walker at each slot. */
+int32_t ising_record_slots(const ising_graph *g, const ising_state *st, int32_t *e_row, void *stream);
+
 /* Totals over all walkers into host out[ISING_N_STATS] (reduces the per-walker
  * counters on the device; synchronises `stream`).                           */
 int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, void *stream);

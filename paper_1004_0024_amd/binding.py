@@ -65,6 +65,7 @@ def lib():
             "pt_swap": ([P, P, i32, P], i32),
             "ising_observables": ([P, P, P, P], i32),
             "ising_stats": ([P, P, P, P], i32),
+            "ising_record_slots": ([P, P, P, P], i32),
             "ising_threshold_row": ([C.c_double, i32, P], i32),
             "ising_level_offsets": ([P, P, P], i32),
             "ising_last_error": ([], C.c_char_p),
@@ -241,6 +242,10 @@ class State:
     def capture(self, n_sweeps, swap_every=1, stream=None, record=False):
         """A HIP graph of `n_sweeps` sweeps from the current counters (see Replay)."""
         return Replay(self, n_sweeps, swap_every, stream, record)
+
+    def record(self, e_row):
+        """e_row[slots] (device int32) = energy of the walker at each slot."""
+        _check(lib().ising_record_slots(self.graph.handle, C.byref(self._s), C.c_void_p(e_row.data_ptr()), _stream()))
 
     def collect_cells(self, n, stride=1, offset=0):
         """Training rows (x [n,17] float32, y [n] uint8) from the current spins."""

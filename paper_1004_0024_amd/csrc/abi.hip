@@ -808,6 +808,14 @@ extern "C" int32_t ising_stats(const ising_graph *g, const ising_state *st, uint
   return ISING_OK;
 }
 
+extern "C" int32_t ising_record_slots(const ising_graph *g, const ising_state *st, int32_t *e_row, void *stream) {
+  if (!g || !e_row) return fail(ISING_E_INVAL, "record_slots: NULL argument");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  HIP_TRY(launch_record(g->dev, dev_state(st), g->n_sys, e_row, (hipStream_t)stream), "record kernel");
+  return ISING_OK;
+}
+
 extern "C" int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream) {
   if (!g) return fail(ISING_E_INVAL, "pt_swap: NULL graph");
   int32_t rc = check_state(st);

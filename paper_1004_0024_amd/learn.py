@@ -1,0 +1,96 @@
+"""Training and use of the learned cell proposal (driver over the C ABI).
+
+Every numeric step runs in the library's kernels: cells are collected from
+the plain chain (ising_collect_cells), the network is trained by its own
+forward/backward and Adam kernels (ising_mlp_grad, ising_mlp_adam), and the
+chain interleaves one plain sweep (+ swap round) with one pass of learned
+cell moves (ising_propose_cells).  This module only sequences the calls.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import ess as _ess
+
+
+def _coprime_stride(total, n):
+    """Smallest stride >= total/n sharing no factor with total: n rows then visit n
+    distinct cells spread over every walker and slice."""
+    st = max(1, total // max(1, n))
+    while math.gcd(st, total) != 1:
+        st += 1
+    return st
+
+
+def collect(state, n_rows, snapshots=4, sweeps_between=10, swap_every=1):
+    """n_rows training rows (x [n,17] float32, y [n] uint8) from `snapshots` states of
+    the plain chain, `sweeps_between` sweeps apart."""
+    import torch
+    total = int(sum(s.M * s.L * s.L * len(s.beta) for s in state.graph.systems if getattr(s, "L", 0)))
+    per = n_rows // snapshots
+    stride = _coprime_stride(total, per)
+    xs, ys = [], []
+    for k in range(snapshots):
+        state.sweep(sweeps_between, swap_every)
+        x, y = state.collect_cells(per, stride=stride, offset=(k * 7919) % total)
+        xs.append(x)
+        ys.append(y)
+    return torch.cat(xs), torch.cat(ys)
+
+
+def train(net, x, y, batch=4096, epochs=2, lr=1e-3):
+    """Minibatch Adam; batch k of an epoch takes rows k, k + nb, k + 2 nb, ... (nb batches),
+    so each batch mixes every snapshot.  Returns the loss of every step (host)."""
+    import torch
+    nb = x.shape[0] // batch
+    if nb == 0:
+        return np.zeros(0)
+    xv = x[:nb * batch].view(batch, nb, x.shape[1]).transpose(0, 1).contiguous()
+    yv = y[:nb * batch].view(batch, nb).transpose(0, 1).contiguous()
+    losses = []
+    for _ in range(epochs):
+        for k in range(nb):
+            losses.append(net.grad_step(xv[k], yv[k]))
+            net.adam(lr)
+    return torch.stack([l.reshape(()) for l in losses]).cpu().numpy()
+
+
+def run(state, steps, net=None, key=0, pass0=0, swap_every=1):
+    """`steps` steps of the chain (a sweep, its swap round, and, with a network, one pass
+    of learned cell moves); returns slot energies [steps, slots] (host) and GPU ms."""
+    import torch
+    g = state.graph
+    e = torch.zeros((steps, g.slots), dtype=torch.int32, device=g.tables.device)
+    moves = torch.zeros((g.R, 2), dtype=torch.int64, device=g.tables.device) if net is not None else None
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for t in range(steps):
+        state.sweep(1, swap_every)
+        if net is not None:
+            state.propose_cells(net, key, pass0 + t, moves)
+        state.record(e[t])
+    t1.record()
+    torch.cuda.synchronize()
+    out = {"e": e.cpu().numpy(), "ms": t0.elapsed_time(t1)}
+    if moves is not None:
+        mv = moves.cpu().numpy()
+        out["acceptance"] = float(mv[:, 1].sum()) / max(1.0, float(mv[:, 0].sum()))
+    return out
+
+
+def ess_summary(graph, series, burn=0.2):
+    """ESS of the energy at the coldest slot of every system (summed) and the median
+    over all slots."""
+    coldest, allv = [], []
+    base = 0
+    for s in graph.systems:
+        K = len(s.beta)
+        col = np.argmax(s.beta)
+        e = _ess.slot_ess(series[:, base:base + K], burn)
+        coldest.append(e[col])
+        allv.extend(e.tolist())
+        base += K
+    return {"coldest_total": float(np.sum(coldest)), "median_slot": float(np.median(allv))}

@@ -4,7 +4,7 @@ against the oracle bit for bit."""
 import numpy as np
 import pytest
 
-from gen import Workload, make_chimera_system
+from gen import Workload, make_chimera_system, make_workload
 
 from .gpu_util import chains_for, compare_system, make_state, say
 
@@ -94,3 +94,20 @@ def test_checkpoint_resume_bit_identical():
     for s, ch in enumerate(chains):
         ch.sweeps(11, 2)
         compare_system(st2, s, ch, "resumed")
+
+
+def test_record_slots_matches_observables():
+    """ising_record_slots writes the running energy of the walker at each slot."""
+    import torch
+    import paper_1004_0024_amd as pa
+    wl = make_workload("C").subset(range(3), n_sweeps=7)
+    st = make_state(wl)
+    st.sweep(7, 1)
+    e = torch.full((st.graph.slots,), -7, dtype=torch.int32, device="cuda")
+    st.record(e)
+    obs = st.observables().cpu().numpy()
+    got = e.cpu().numpy()
+    want = np.zeros_like(got)
+    want[obs[:, 3]] = obs[:, 2]
+    assert np.array_equal(got, want)
+    assert np.array_equal(obs[:, 0], obs[:, 2])

@@ -264,14 +264,15 @@ int32_t ising_collect_cells(const ising_graph *g, const ising_state *st, int64_t
 /* One pass of cell moves over every walker: the colour classes of cells in
  * order (cells of one class share no edge and move at once); each cell gets a
  * joint proposal from the network and the Metropolis-Hastings test.  Uniforms:
- * Philox4x64-10 with key (key, walker), counters (pass_index, cell, 0, 0) and
- * (pass_index, cell, 1, 0): high halves of the eight words are the proposal
- * uniforms, the low half of the first word the acceptance uniform.  Energies
- * are kept exact.  `work` (device, caller-owned) holds ising_propose_bytes
- * bytes; moves (device, nullable) [R][2] += proposals, acceptances.          */
-int32_t ising_propose_bytes(const ising_graph *g, size_t *bytes);
+ * Philox4x32-10 with key (key mod 2^32, key div 2^32) and counters (cell,
+ * walker, pass_index, j) for blocks j = 0, 1, 2: the eight words of blocks 0
+ * and 1 are the proposal uniforms, word 0 of block 2 the acceptance uniform
+ * (uniform = word * 2^-32); 0 <= pass_index < 2^32, else ISING_E_RANGE.  Energies
+ * are kept exact.  One launch per colour class: boundary fields, network and
+ * test run in one kernel, with no device memory besides the state and the
+ * network.  moves (device, nullable) [R][2] += proposals, acceptances.      */
 int32_t ising_propose_cells(const ising_graph *g, ising_state *st, const ising_mlp *net, uint64_t key,
-                            int64_t pass_index, void *work, size_t work_bytes, uint64_t *moves, void *stream);
+                            int64_t pass_index, uint64_t *moves, void *stream);
 
 /* ---- host-only helpers (no device work; usable without a GPU) ------------ */
 

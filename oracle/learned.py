@@ -16,7 +16,10 @@ and accepted with the exact Metropolis-Hastings probability
   min(1, exp(-beta dE) q(s) / q(s'))    (cost function of Section 1),
 dE = E_c(s') - E_c(s), E_c(s) = -sum_k b_k s_k - sum_{in-cell edges} J s s.
 Training minimises the mean of -log q(s_cell | b, beta) over cells drawn from
-the plain chain.  Uniforms come from Philox4x64-10 (Salmon et al., SC'11).
+the plain chain.  Uniforms come from Philox4x32-10 (Salmon et al., SC'11):
+key (key mod 2^32, key div 2^32), counters (cell, walker, pass, j) for blocks
+j = 0, 1, 2; the words of blocks 0 and 1 are the 8 proposal uniforms, word 0
+of block 2 the acceptance uniform.
 """
 from __future__ import annotations
 
@@ -24,31 +27,36 @@ import numpy as np
 
 from gen.mlp import SHAPES
 
-# ----------------------------------------------------------------- Philox4x64
-_M0, _M1 = 0xD2E7470EE14C6C93, 0xCA5A826395121157
-_W0, _W1 = 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B
-_MASK = (1 << 64) - 1
+# ----------------------------------------------------------------- Philox4x32
+_M0, _M1 = 0xD2511F53, 0xCD9E8D57          # round multipliers
+_W0, _W1 = 0x9E3779B9, 0xBB67AE85          # key schedule (Weyl) increments
+_MASK = (1 << 32) - 1
 
 
-def philox4x64(counter, key):
-    """One Philox4x64-10 block: four 64-bit words for a 256-bit counter, 128-bit key."""
+def philox4x32(counter, key, rounds=10):
+    """One Philox4x32 block: four 32-bit words for a 128-bit counter and a 64-bit key.
+    A round multiplies words 0 and 2 by the two constants (full 64-bit products),
+    then the new words are (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key
+    advances by the Weyl increments between rounds."""
     x = [int(c) & _MASK for c in counter]
     k0, k1 = int(key[0]) & _MASK, int(key[1]) & _MASK
-    for r in range(10):
+    for r in range(rounds):
         if r:
             k0 = (k0 + _W0) & _MASK
             k1 = (k1 + _W1) & _MASK
         p0, p1 = _M0 * x[0], _M1 * x[2]
-        x = [(p1 >> 64) ^ x[1] ^ k0, p1 & _MASK, (p0 >> 64) ^ x[3] ^ k1, p0 & _MASK]
+        x = [(p1 >> 32) ^ x[1] ^ k0, p1 & _MASK, (p0 >> 32) ^ x[3] ^ k1, p0 & _MASK]
     return x
 
 
 def cell_uniforms(key_base, walker, pass_index, cell):
     """The 9 uniforms of one cell proposal: u[0..7] for the proposed spins, u[8] for
     the acceptance; 32-bit integers (uniform = u * 2^-32)."""
-    w = philox4x64((pass_index, cell, 0, 0), (key_base, walker)) + \
-        philox4x64((pass_index, cell, 1, 0), (key_base, walker))
-    return [v >> 32 for v in w] + [w[0] & 0xFFFFFFFF]
+    key = (key_base & _MASK, (key_base >> 32) & _MASK)
+    w = []
+    for j in range(3):
+        w += philox4x32((cell, walker, pass_index, j), key)
+    return w[:9]
 
 
 # ----------------------------------------------------------------- MLP

@@ -81,8 +81,7 @@ def lib():
             "ising_mlp_grad": ([P, P, P, i32, P, P], i32),
             "ising_mlp_adam": ([P, C.c_float, P], i32),
             "ising_collect_cells": ([P, P, i64, i64, i32, P, P, P], i32),
-            "ising_propose_bytes": ([P, P], i32),
-            "ising_propose_cells": ([P, P, P, C.c_uint64, i64, P, sz, P, P], i32),
+            "ising_propose_cells": ([P, P, P, C.c_uint64, i64, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -259,14 +258,9 @@ class State:
 
     def propose_cells(self, net, key, pass_index, moves=None):
         """One pass of learned cell moves (all colour classes)."""
-        import torch
-        if getattr(self, "_work", None) is None:
-            nb = C.c_size_t(0)
-            _check(lib().ising_propose_bytes(self.graph.handle, C.byref(nb)))
-            self._work = torch.empty(int(nb.value), dtype=torch.uint8, device=self.graph.tables.device)
         _check(lib().ising_propose_cells(self.graph.handle, C.byref(self._s), C.byref(net._s), C.c_uint64(key),
-                                         int(pass_index), C.c_void_p(self._work.data_ptr()), self._work.numel(),
-                                         C.c_void_p(moves.data_ptr()) if moves is not None else None, _stream()))
+                                         int(pass_index), C.c_void_p(moves.data_ptr()) if moves is not None else None,
+                                         _stream()))
 
     def swap(self, parity):
         _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))

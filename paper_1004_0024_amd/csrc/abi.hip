@@ -251,12 +251,13 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, total;
+  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, total;
 };
 
 // Device tables.  Room for one tile per walker, so any launch shape can be
 // installed later without reallocating.
-static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R, int64_t n_cells) {
+static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R, int64_t n_cells,
+                         int64_t cell_rows) {
   Layout L{};
   size_t o = 0;
   n_tiles = std::max(n_tiles, R);
@@ -276,6 +277,8 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   o = align256(o + sizeof(int32_t) * R);
   L.cells = o;
   o = align256(o + sizeof(uint16_t) * std::max<int64_t>(n_cells, 1));
+  L.rtiles = o;
+  o = align256(o + sizeof(int32_t) * std::max<int64_t>(cell_rows / 64, 1));
   L.total = o;
   return L;
 }
@@ -349,9 +352,9 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     for (int p = 0; p < 5; ++p) si.pc[p] = h.pc[p];
     si.rows = 0;
     for (int p = 0; p < h.n_phases; ++p) si.rows = std::max(si.rows, h.pc[p + 1] - h.pc[p]);
-    si.row0 = g.cell_rows;
+    si.row0 = g.cell_rows;  // a multiple of 64: a 64-row tile of cell moves lies in one system
     si.cell0 = g.total_cells;
-    g.cell_rows += (int64_t)si.rows * h.K;
+    g.cell_rows += ((int64_t)si.rows * h.K + 63) / 64 * 64;
     g.total_cells += h.grid_L ? (int64_t)h.grid_L * h.grid_L * h.M * h.K : 0;
     g.max_phases = std::max(g.max_phases, h.n_phases);
     cl += (int64_t)h.cells.size();
@@ -421,7 +424,7 @@ extern "C" int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys
     ntm += h.S;
     ncl += (int64_t)h.cells.size();
   }
-  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl).total;
+  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl, g.cell_rows).total;
   return ISING_OK;
 }
 
@@ -444,7 +447,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
     ntm += h.S;
     ncl += (int64_t)h.cells.size();
   }
-  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl);
+  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl, g->cell_rows);
   if (bytes < L.total) {
     delete g;
     return fail(ISING_E_SIZE, "dev_tables has %zu bytes, needs %zu", bytes, L.total);
@@ -484,6 +487,14 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
       co += h.cells.size();
     }
   }
+  {  // system of each 64-row tile of cell moves: the last system whose rows start at or before it
+    int32_t *ts = (int32_t *)(host.data() + L.rtiles);
+    int32_t sidx = 0;
+    for (int64_t t = 0; t < g->cell_rows / 64; ++t) {
+      while (sidx + 1 < n_sys && g->sys[sidx + 1].row0 <= t * 64) ++sidx;
+      ts[t] = sidx;
+    }
+  }
   memcpy(host.data() + L.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size());
   memcpy(host.data() + L.wsys, g->walker_sys.data(), sizeof(int32_t) * g->walker_sys.size());
   hipStream_t st = (hipStream_t)stream;
@@ -502,6 +513,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.walker_sys = (const int32_t *)(base + L.wsys);
   g->dev.fifo = (const uint32_t *)(base + L.fifo);
   g->dev.cells = (const uint16_t *)(base + L.cells);
+  g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
   g->bytes = L.total;
   *out = g;
   return ISING_OK;
@@ -883,54 +895,20 @@ extern "C" int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream) {
 // ---------------------------------------------------------------------------
 // Learned cell proposal: cells of the chain
 // ---------------------------------------------------------------------------
-struct ProposeWork {
-  size_t x, logits, b, total;
-};
-
-static ProposeWork propose_layout(int64_t rows) {
-  ProposeWork w{};
-  size_t o = 0;
-  w.x = o;
-  o = align256(o + sizeof(float) * kIn * rows);
-  w.logits = o;
-  o = align256(o + sizeof(float) * kOut * rows);
-  w.b = o;
-  o = align256(o + 8 * rows);
-  w.total = o;
-  return w;
-}
-
-extern "C" int32_t ising_propose_bytes(const ising_graph *g, size_t *bytes) {
-  if (!g || !bytes) return fail(ISING_E_INVAL, "propose_bytes: NULL argument");
-  if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
-  *bytes = propose_layout(g->cell_rows).total;
-  return ISING_OK;
-}
-
 extern "C" int32_t ising_propose_cells(const ising_graph *g, ising_state *st, const ising_mlp *net, uint64_t key,
-                                       int64_t pass_index, void *work, size_t work_bytes, uint64_t *moves,
-                                       void *stream) {
-  if (!g || !work) return fail(ISING_E_INVAL, "propose_cells: NULL argument");
+                                       int64_t pass_index, uint64_t *moves, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "propose_cells: NULL graph");
   int32_t rc = check_state(st);
   if (rc) return rc;
   rc = check_mlp(net);
   if (rc) return rc;
   if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
-  const ProposeWork lay = propose_layout(g->cell_rows);
-  if (work_bytes < lay.total) return fail(ISING_E_SIZE, "propose work has %zu bytes, needs %zu", work_bytes, lay.total);
-  if (g->cell_rows > INT32_MAX) return fail(ISING_E_RANGE, "too many cells for one pass");
+  if (pass_index < 0 || pass_index > (int64_t)UINT32_MAX) return fail(ISING_E_RANGE, "pass_index must fit 32 bits");
   hipStream_t s = (hipStream_t)stream;
-  DevState d = dev_state(st);
-  uint8_t *base = (uint8_t *)work;
-  float *x = (float *)(base + lay.x);
-  float *logits = (float *)(base + lay.logits);
-  int8_t *b = (int8_t *)(base + lay.b);
-  for (int32_t p = 0; p < g->max_phases; ++p) {
-    HIP_TRY(launch_cell_features(g->dev, d, g->n_sys, g->cell_rows, p, x, b, s), "cell features");
-    HIP_TRY(launch_mlp_forward(net->w, net->wb, x, (int32_t)g->cell_rows, logits, s), "cell proposals");
-    HIP_TRY(launch_cell_accept(g->dev, d, g->n_sys, g->cell_rows, p, logits, b, key, pass_index, moves, s),
-            "cell acceptance");
-  }
+  const DevState d = dev_state(st);
+  for (int32_t p = 0; p < g->max_phases; ++p)
+    HIP_TRY(launch_cell_propose(g->dev, d, g->n_sys, g->cell_rows, p, net->w, net->wb, key, pass_index, moves, s),
+            "cell moves");
   return ISING_OK;
 }
 

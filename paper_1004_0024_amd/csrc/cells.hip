@@ -4,32 +4,31 @@
 //
 // A phase is one colour class of cells: cells of one colour share no edge, so
 // all of them (in every walker) are updated at once; the phases run in order.
-// Uniforms come from Philox4x64-10 (Salmon et al., SC'11): key (key, walker),
-// counters (pass, cell, 0, 0) and (pass, cell, 1, 0) give eight 64-bit words;
-// the high halves are the 8 proposal uniforms, the low half of the first word
-// the acceptance uniform.
+// Uniforms come from Philox4x32-10 (Salmon et al., SC'11): key (key mod 2^32,
+// key div 2^32), counters (cell, walker, pass, j) for blocks j = 0, 1, 2; the
+// words of blocks 0 and 1 are the 8 proposal uniforms, word 0 of block 2 the
+// acceptance uniform.
 #include "internal.h"
 #include "mlp.h"
 
 namespace ising {
 
-// ---- Philox4x64-10 -----------------------------------------------------------
-__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+// ---- Philox4x32-10 -----------------------------------------------------------
+__device__ __forceinline__ void philox4x32(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {
       k0 += W0;
       k1 += W1;
     }
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t x0 = hi1 ^ c[1] ^ k0, x2 = hi0 ^ c[3] ^ k1;
+    const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+    const uint32_t x0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, x2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
     c[0] = x0;
-    c[1] = lo1;
+    c[1] = (uint32_t)p1;
     c[2] = x2;
-    c[3] = lo0;
+    c[3] = (uint32_t)p0;
   }
 }
 
@@ -47,20 +46,32 @@ __device__ __forceinline__ int find_system(const SysInfo *sys, int n_sys, int64_
 }
 
 // Boundary fields b_k = h_k + sum_{j outside the cell} J_kj s_j of cell c of slice m.
+// A template record is read as two 16-byte words (neighbours; couplings, h,
+// J_tau, level, degree, packed in-cell couplings) and unpacked in registers.
 __device__ __forceinline__ void boundary_fields(const DevTables &T, const SysInfo &sy, const uint32_t *sp, int m,
                                                 int c, int b[8]) {
   auto bit = [&](int mm, int q) { return (int)((sp[mm * sy.RS + (q >> 5)] >> (q & 31)) & 1u); };
   const int M = sy.M;
   const int mp = m == 0 ? M - 1 : m - 1, mn = m == M - 1 ? 0 : m + 1;
   const bool has_p = M > 1 && (m > 0 || sy.ring), has_n = M > 1 && (m < M - 1 || sy.ring);
+  const uint4 *rec = (const uint4 *)(T.tmpl + sy.tmpl0 + c * 8);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int q = c * 8 + k;
-    const TmplSpin ts = T.tmpl[sy.tmpl0 + q];
-    int f = ts.h;
-    for (int j = 4; j < ts.deg; ++j) f += ts.J[j] * (2 * bit(m, ts.nbr[j]) - 1);  // first 4: in-cell partners
-    if (has_p) f += ts.Jtau * (2 * bit(mp, q) - 1);
-    if (has_n) f += ts.Jtau * (2 * bit(mn, q) - 1);
+    const uint4 lo = rec[2 * k], hi = rec[2 * k + 1];  // lo: nbr[0..7]; hi: J[0..7], h, Jtau, f, deg, jpack
+    const int deg = (int)(hi.z >> 24);
+    const int jtau = (int)(int8_t)((hi.z >> 8) & 0xffu);
+    int f = (int)(int8_t)(hi.z & 0xffu);
+#pragma unroll
+    for (int j = 4; j < kMaxDeg; ++j) {  // the first 4 neighbours are the in-cell partners
+      if (j < deg) {
+        const int nb = (int)(int16_t)((((j < 6) ? lo.z : lo.w) >> (16 * (j & 1))) & 0xffffu);
+        const int Jv = (int)(int8_t)((hi.y >> (8 * (j - 4))) & 0xffu);
+        f += Jv * (2 * bit(m, nb) - 1);
+      }
+    }
+    if (has_p) f += jtau * (2 * bit(mp, q) - 1);
+    if (has_n) f += jtau * (2 * bit(mn, q) - 1);
     b[k] = f;
   }
 }
@@ -73,43 +84,6 @@ __device__ __forceinline__ void write_features(float *x, const int b[8], float b
   }
   x[16] = beta;
 }
-
-// ---- features of the cells of one phase (one row per walker and phase cell) ----
-__global__ void cell_features_kernel(DevTables T, DevState St, int32_t n_sys, int64_t rows_total, int32_t phase,
-                                     float *X, int8_t *B) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows_total) return;
-  const SysInfo sy = T.sys[find_system<true>(T.sys, n_sys, row)];
-  const int64_t local = row - sy.row0;
-  const int w = (int)(local / sy.rows), j = (int)(local % sy.rows);
-  float *x = X + row * kIn;
-  int8_t *bo = B + row * 8;
-  const int count = phase < sy.n_phases ? sy.pc[phase + 1] - sy.pc[phase] : 0;
-  if (j >= count) {
-    for (int k = 0; k < kIn; ++k) x[k] = 0.f;
-    for (int k = 0; k < 8; ++k) bo[k] = 0;
-    return;
-  }
-  const int ci = T.cells[sy.cl0 + sy.pc[phase] + j];
-  const int LL = sy.grid_L * sy.grid_L;
-  const int m = ci / LL, c = ci - m * LL;
-  const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)w * sy.WW;
-  int b[8];
-  boundary_fields(T, sy, sp, m, c, b);
-  write_features(x, b, (float)T.beta[sy.slot0 + St.temp_of[sy.walker0 + w]]);
-  for (int k = 0; k < 8; ++k) bo[k] = (int8_t)b[k];
-}
-
-hipError_t launch_cell_features(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
-                                int32_t phase, float *x, int8_t *b, hipStream_t st) {
-  if (rows_total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cell_features_kernel, dim3((unsigned)((rows_total + 255) / 256)), dim3(256), 0, st, t, s,
-                     n_sys, rows_total, phase, x, b);
-  return hipGetLastError();
-}
-
-// ---- Metropolis-Hastings acceptance of the proposals of one phase -------------
-__device__ __forceinline__ float log_sigmoid_f(float v) { return fminf(v, 0.f) - log1pf(expf(-fabsf(v))); }
 
 // E_c(s) = -sum_k b_k s_k - sum over in-cell edges J s s (bit k of `byte` = spin k is +1).
 __device__ __forceinline__ int cell_energy(uint32_t byte, const int b[8], const int jin[16]) {
@@ -124,90 +98,274 @@ __device__ __forceinline__ int cell_energy(uint32_t byte, const int b[8], const 
   return e;
 }
 
-__global__ void cell_accept_kernel(DevTables T, DevState St, int32_t n_sys, int64_t rows_total, int32_t phase,
-                                   const float *logits, const int8_t *B, uint64_t key, int64_t pass_index,
-                                   uint64_t *moves) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = row < rows_total;
-  int r = -1, dE = 0;
-  bool accept = false;
-  if (valid) {
-    const SysInfo sy = T.sys[find_system<true>(T.sys, n_sys, row)];
-    const int64_t local = row - sy.row0;
-    const int w = (int)(local / sy.rows), j = (int)(local % sy.rows);
+// ---- one colour class of cell moves in one launch -----------------------------
+// Each wavefront takes tiles of 64 rows (row = walker x cell of the class, one
+// lane per row): the lane computes its cell's boundary fields and writes the
+// BF16 network input to LDS; the three layers run on 16x16x32 BF16 matrix
+// cores with the rows as the N side (four 16-row tiles), so that a layer's
+// results stay in the lanes that feed them to the next layer; the logits go
+// back through LDS to the row's lane, which draws the proposal and takes the
+// Metropolis-Hastings decision.
+//
+// Result tiles: lane l holds units 4(l/16) + j (j < 4) of row l % 16.  The
+// next layer's B operand wants, in lane l, 8 consecutive positions of the
+// contraction axis for row l % 16; the contraction order is free, so position
+// 32kk + 8g + p (g = l/16) is taken to be unit 32kk + 4g + p for p < 4 and
+// 32kk + 16 + 4g + (p - 4) for p >= 4 -- exactly what the lane holds from
+// result tiles 2kk and 2kk + 1 -- and the weight columns are stored in that
+// order.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int unit_at(int c) {
+  const int kk = c >> 5, g = (c >> 3) & 3, p = c & 7;
+  return (kk << 5) + (p < 4 ? 4 * g + p : 16 + 4 * g + (p - 4));
+}
+
+// Row strides are padded by 8 BF16 (16 bytes): the 16 rows that one matrix
+// operand read touches then fall on distinct LDS banks.
+constexpr int kS1 = 40, kS2 = 136;
+struct alignas(16) ProposeLds {
+  uint16_t W1[128 * kS1];  // [unit][input], inputs padded to 32
+  uint16_t W2[128 * kS2];  // [unit][position], positions in unit_at order
+  uint16_t W3[16 * kS2];   // [output (8 + 8 zero rows)][position]
+  float b1[128], b2[128], b3[16];
+  uint16_t X[4][64 * kS1];  // per wavefront: inputs of its 64 rows, then their logits
+};
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// relu of two FP32 values, as packed BF16 (round to nearest even).  The
+// rounding keeps the sign, so relu is applied after it: read as 16-bit
+// integers, BF16 values below zero (and -0) are negative, and a packed
+// integer max with 0 clears exactly those.
+__device__ __forceinline__ uint32_t relu_bf2(float a, float b) {
+  const i16x2 v = __builtin_bit_cast(i16x2, __builtin_convertvector((f32x2{a, b}), bf16x2));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (i16x2{0, 0})));
+}
+
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
+}
+
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                  0, 0);
+}
+
+__global__ void __launch_bounds__(256, 2)
+    cell_propose_kernel(DevTables T, DevState St, int32_t n_sys, int64_t rows_total, int32_t phase, const float *w,
+                        const uint16_t *wb, uint64_t key, int64_t pass_index, uint64_t *moves) {
+  __shared__ ProposeLds s;
+  // 16-byte pieces: W1 rows as they are; for W2 and W3 the 8 positions (kk, g, 0..7)
+  // are units 32kk + 4g + 0..3 and 32kk + 16 + 4g + 0..3, two 8-byte pieces.
+  for (int i = threadIdx.x; i < 128 * 4; i += blockDim.x)
+    *(uint4 *)(s.W1 + (i >> 2) * kS1 + (i & 3) * 8) = *(const uint4 *)(wb + kPW1 + i * 8);
+  for (int i = threadIdx.x; i < 144 * 16; i += blockDim.x) {
+    const int row = i >> 4, kk = (i >> 2) & 3, gg = i & 3;  // rows 0..127 of W2, then 0..15 of W3
+    const uint16_t *src = row < 128 ? wb + kPW2 + row * 128 : wb + kPW3 + (row - 128) * 128;
+    uint16_t *dst = row < 128 ? s.W2 + row * kS2 : s.W3 + (row - 128) * kS2;
+    const uint2 a = *(const uint2 *)(src + kk * 32 + 4 * gg), b = *(const uint2 *)(src + kk * 32 + 16 + 4 * gg);
+    *(uint4 *)(dst + kk * 32 + gg * 8) = uint4{a.x, a.y, b.x, b.y};
+  }
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    s.b1[i] = w[kOB1 + i];
+    s.b2[i] = w[kOB2 + i];
+  }
+  for (int i = threadIdx.x; i < 16; i += blockDim.x) s.b3[i] = i < kOut ? w[kOB3 + i] : 0.f;
+  __syncthreads();
+
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, n16 = l & 15, g = l >> 4;
+  uint16_t *X = s.X[wv];
+  const int64_t tiles = rows_total / 64;  // rows_total is a multiple of 64
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+    // ---- this lane's row: locate the cell, boundary fields, input ----
+    // a tile lies in one system: its record is read once for the wavefront
+    const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
+    const SysInfo &sy = T.sys[sidx];
+    const int64_t row = tile * 64 + l;
+    // rows of one system: K x rows < 2^31 (a walker's spins fit in LDS)
+    const uint32_t local = (uint32_t)(row - sy.row0);
+    const uint32_t rows = (uint32_t)sy.rows;
+    const int wk = (int)(local / rows), j = (int)(local - (uint32_t)wk * rows);
     const int count = phase < sy.n_phases ? sy.pc[phase + 1] - sy.pc[phase] : 0;
-    valid = j < count;
+    const bool valid = wk < sy.K && j < count;
+    int r = -1, ci = 0;
+    int b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    float beta = 0.f;
+    uint8_t *bytep = nullptr;
+    uint32_t cur = 0;
+    int jt = 0;  // template index of the cell's first spin
     if (valid) {
-      r = sy.walker0 + w;
-      const int ci = T.cells[sy.cl0 + sy.pc[phase] + j];
+      r = sy.walker0 + wk;
+      ci = T.cells[sy.cl0 + sy.pc[phase] + j];
       const int LL = sy.grid_L * sy.grid_L;
       const int m = ci / LL, c = ci - m * LL;
-      uint8_t *bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)w * sy.WW + m * sy.RS + ((c * 8) >> 5)) + (c & 3);
-      const uint32_t cur = *bytep;
-      int b[8], jin[16];
-      for (int k = 0; k < 8; ++k) b[k] = B[row * 8 + k];
-      for (int k = 0; k < 4; ++k) {
-        const int32_t pack = T.tmpl[sy.tmpl0 + c * 8 + k].jpack;  // 2J to partners 4..7
-        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((pack >> (8 * i)) & 0xff)) / 2;
+      const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)wk * sy.WW;
+      boundary_fields(T, sy, sp, m, c, b);
+      bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)wk * sy.WW + m * sy.RS + ((c * 8) >> 5)) + (c & 3);
+      cur = *bytep;
+      beta = (float)T.beta[sy.slot0 + St.temp_of[r]];
+      jt = sy.tmpl0 + c * 8;
+    }
+    {
+      u32x4 *xr = (u32x4 *)(X + l * kS1);
+      const u32x4 zero = {0u, 0u, 0u, 0u};
+      xr[0] = zero;
+      xr[1] = u32x4{pack_bf2(b[0] * 0.125f, b[1] * 0.125f), pack_bf2(b[2] * 0.125f, b[3] * 0.125f),
+                    pack_bf2(b[4] * 0.125f, b[5] * 0.125f), pack_bf2(b[6] * 0.125f, b[7] * 0.125f)};
+      xr[2] = u32x4{(uint32_t)f2bf(beta), 0u, 0u, 0u};
+      xr[3] = zero;
+    }
+    wave_fence();
+
+    // ---- layer 1: 8 unit tiles x 4 row tiles ----
+    u32x4 xb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xb[t] = *(const u32x4 *)(X + (t * 16 + n16) * kS1 + g * 8);
+    u32x4 h1[4][4];
+    u32x4 w1f[8];
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) w1f[ft] = *(const u32x4 *)(s.W1 + (ft * 16 + n16) * kS1 + g * 8);
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) {
+      const u32x4 a = w1f[ft];
+      const f32x4 bias = *(const f32x4 *)(s.b1 + ft * 16 + 4 * g);  // bias enters as the initial sum
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const f32x4 acc = mfma16(a, xb[t], bias);
+        h1[ft >> 1][t][(ft & 1) * 2] = relu_bf2(acc[0], acc[1]);
+        h1[ft >> 1][t][(ft & 1) * 2 + 1] = relu_bf2(acc[2], acc[3]);
       }
+    }
+    // ---- layer 2 (the next unit tile's weights are read while this one multiplies) ----
+    u32x4 h2[4][4];
+    u32x4 wa[4], wn[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) wa[kk] = *(const u32x4 *)(s.W2 + n16 * kS2 + kk * 32 + g * 8);
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) {
+      if (ft < 7) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) wn[kk] = *(const u32x4 *)(s.W2 + ((ft + 1) * 16 + n16) * kS2 + kk * 32 + g * 8);
+      }
+      f32x4 acc[4];
+      const f32x4 bias = *(const f32x4 *)(s.b2 + ft * 16 + 4 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = bias;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = mfma16(wa[kk], h1[kk][t], acc[t]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        h2[ft >> 1][t][(ft & 1) * 2] = relu_bf2(acc[t][0], acc[t][1]);
+        h2[ft >> 1][t][(ft & 1) * 2 + 1] = relu_bf2(acc[t][2], acc[t][3]);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) wa[kk] = wn[kk];
+    }
+    // ---- layer 3: logits (outputs 8..15 are zero padding) ----
+    f32x4 acc3[4];
+    const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc3[t] = bias3;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const u32x4 a = *(const u32x4 *)(s.W3 + n16 * kS2 + kk * 32 + g * 8);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc3[t] = mfma16(a, h2[kk][t], acc3[t]);
+    }
+    wave_fence();  // every lane has read its inputs: the region now takes logits
+    float *Lg = (float *)X;
+    if (g < 2) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Lg[(t * 16 + n16) * 8 + 4 * g + j] = acc3[t][j];
+    }
+    wave_fence();
+
+    // ---- proposal and Metropolis-Hastings test of this lane's cell ----
+    int dE = 0;
+    bool accept = false;
+    if (valid) {
       float lg[8];
-      for (int k = 0; k < 8; ++k) lg[k] = logits[row * kOut + k];
-      uint64_t c0[4] = {(uint64_t)pass_index, (uint64_t)ci, 0ull, 0ull};
-      uint64_t c1[4] = {(uint64_t)pass_index, (uint64_t)ci, 1ull, 0ull};
-      philox4x64(c0, key, (uint64_t)r);
-      philox4x64(c1, key, (uint64_t)r);
-      const uint64_t wd[8] = {c0[0], c0[1], c0[2], c0[3], c1[0], c1[1], c1[2], c1[3]};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lg[k] = Lg[l * 8 + k];
+      int jin[16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t pk = T.tmpl[jt + k].jpack;  // 2J to partners 4..7
+#pragma unroll
+        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((pk >> (8 * i)) & 0xff)) / 2;
+      }
+      const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+      uint32_t wd[12];
+#pragma unroll
+      for (int blk = 0; blk < 3; ++blk) {
+        uint32_t c4[4] = {(uint32_t)ci, (uint32_t)r, (uint32_t)pass_index, (uint32_t)blk};
+        philox4x32(c4, k0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wd[4 * blk + q] = c4[q];
+      }
       uint32_t nb = 0;
-      float lq_new = 0.f, lq_cur = 0.f;
+      float lratio = 0.f;  // log q(current) - log q(proposed)
+#pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const float u = (float)(uint32_t)(wd[k] >> 32) * 0x1p-32f;
-        const float p = 1.f / (1.f + expf(-lg[k]));
-        const bool up = u < p;
+        const float u = (float)wd[k] * 0x1p-32f;
+        const bool up = u < 1.f / (1.f + expf(-lg[k]));
         nb |= (up ? 1u : 0u) << k;
-        lq_new += log_sigmoid_f(up ? lg[k] : -lg[k]);
-        lq_cur += log_sigmoid_f(((cur >> k) & 1u) ? lg[k] : -lg[k]);
+        // log s(x) - log s(-x) = x: only the spins that change contribute
+        const bool was_up = (cur >> k) & 1u;
+        if (up != was_up) lratio += was_up ? lg[k] : -lg[k];
       }
       dE = cell_energy(nb, b, jin) - cell_energy(cur, b, jin);
-      const float beta = (float)T.beta[sy.slot0 + St.temp_of[r]];
-      const float la = -beta * (float)dE + lq_cur - lq_new;
-      const float ua = (float)(uint32_t)(wd[0] & 0xffffffffull) * 0x1p-32f;
+      const float la = -beta * (float)dE + lratio;
+      const float ua = (float)wd[8] * 0x1p-32f;
       accept = la >= 0.f || ua < expf(la);
       if (accept && nb != cur) *bytep = (uint8_t)nb;
       if (!accept) dE = 0;
     }
-  }
-  // per-walker sums: one atomic per wavefront when its lanes share a walker
-  const int r0 = __shfl(r, 0);
-  const bool uniform = __all(r == r0);
-  if (uniform) {
-    if (r0 >= 0) {
-      int tot = dE;
-      for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-      const unsigned long long na = __popcll(__ballot(valid && accept));
-      const unsigned long long nv = __popcll(__ballot(valid));
-      if ((threadIdx.x & 63) == 0) {
-        if (tot) atomicAdd(&St.energy[r0], tot);
-        if (moves) {
-          atomicAdd((unsigned long long *)&moves[2 * (size_t)r0], nv);
-          atomicAdd((unsigned long long *)&moves[2 * (size_t)r0 + 1], na);
+    wave_fence();  // logits read before the next tile's inputs overwrite them
+
+    // per-walker sums: one atomic per wavefront when its lanes share a walker
+    const int r0 = __shfl(r, 0);
+    const bool uniform = __all(r == r0);
+    if (uniform) {
+      if (r0 >= 0) {
+        int tot = dE;
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+        const unsigned long long na = __popcll(__ballot(valid && accept));
+        const unsigned long long nv = __popcll(__ballot(valid));
+        if (l == 0) {
+          if (tot) atomicAdd(&St.energy[r0], tot);
+          if (moves) {
+            atomicAdd((unsigned long long *)&moves[2 * (size_t)r0], nv);
+            atomicAdd((unsigned long long *)&moves[2 * (size_t)r0 + 1], na);
+          }
         }
       }
-    }
-  } else if (valid) {
-    if (dE) atomicAdd(&St.energy[r], dE);
-    if (moves) {
-      atomicAdd((unsigned long long *)&moves[2 * (size_t)r], 1ull);
-      if (accept) atomicAdd((unsigned long long *)&moves[2 * (size_t)r + 1], 1ull);
+    } else if (valid) {
+      if (dE) atomicAdd(&St.energy[r], dE);
+      if (moves) {
+        atomicAdd((unsigned long long *)&moves[2 * (size_t)r], 1ull);
+        if (accept) atomicAdd((unsigned long long *)&moves[2 * (size_t)r + 1], 1ull);
+      }
     }
   }
 }
 
-hipError_t launch_cell_accept(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
-                              int32_t phase, const float *logits, const int8_t *b, uint64_t key,
-                              int64_t pass_index, uint64_t *moves, hipStream_t st) {
+hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
+                               int32_t phase, const float *w, const uint16_t *wb, uint64_t key, int64_t pass_index,
+                               uint64_t *moves, hipStream_t st) {
   if (rows_total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cell_accept_kernel, dim3((unsigned)((rows_total + 255) / 256)), dim3(256), 0, st, t, s, n_sys,
-                     rows_total, phase, logits, b, key, pass_index, moves);
+  const int64_t tiles = rows_total / 64;
+  const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 512);
+  hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(256), 0, st, t, s, n_sys, rows_total, phase, w, wb, key,
+                     pass_index, moves);
   return hipGetLastError();
 }
 

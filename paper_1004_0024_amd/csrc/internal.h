@@ -93,6 +93,7 @@ struct DevTables {
   const int32_t *walker_sys;  // [R] system of each walker
   const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
   const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
+  const int32_t *tile_sys;    // per 64-row tile of cell moves: its system
 };
 
 struct DevState {
@@ -114,11 +115,9 @@ hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, i
                          hipStream_t st);
 hipError_t launch_observables(const DevTables &t, const DevState &s, int32_t R, int32_t *obs,
                               int32_t set_energy, hipStream_t st);
-hipError_t launch_cell_features(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
-                                int32_t phase, float *x, int8_t *b, hipStream_t st);
-hipError_t launch_cell_accept(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total, int32_t phase,
-                              const float *logits, const int8_t *b, uint64_t key, int64_t pass_index,
-                              uint64_t *moves, hipStream_t st);
+hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
+                               int32_t phase, const float *w, const uint16_t *wb, uint64_t key, int64_t pass_index,
+                               uint64_t *moves, hipStream_t st);
 hipError_t launch_collect_cells(const DevTables &t, const DevState &s, int32_t n_sys, int64_t stride,
                                 int64_t offset, int64_t total_cells, int32_t n, float *x, uint8_t *y,
                                 hipStream_t st);

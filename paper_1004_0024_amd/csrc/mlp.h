@@ -22,6 +22,22 @@ constexpr int kPW3T = kPW3 + 16 * 128;
 constexpr int kPW2T = kPW3T + 128 * 32;
 constexpr int kPackEnd = kPW2T + 128 * 128;  // 43,008
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite values).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 hipError_t launch_mlp_pack(const float *w, uint16_t *wb, hipStream_t st);
 hipError_t launch_mlp_forward(const float *w, const uint16_t *wb, const float *x, int32_t n, float *logits,
                               hipStream_t st);

@@ -14,16 +14,6 @@
 
 namespace ising {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
 // acc[16x16] += A[16 x 32] * B[32 x 16].  A is row-major [i][k] with row stride
 // sa, B is given as its transpose Bt [n][k] with row stride sb (both in BF16
 // elements, strides multiples of 8).  Lane l supplies A[l%16][8(l/16) .. +8)
@@ -34,11 +24,6 @@ __device__ __forceinline__ f32x4 mma(const uint16_t *A, int sa, const uint16_t *
   const bf16x8 a = *(const bf16x8 *)(A + (l & 15) * sa + ((l >> 4) << 3));
   const bf16x8 b = *(const bf16x8 *)(Bt + (l & 15) * sb + ((l >> 4) << 3));
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-}
-
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // ---- FP32 master weights -> packed BF16 copies ----------------------------

@@ -101,13 +101,15 @@ def test_record_slots_matches_observables():
     import torch
     import paper_1004_0024_amd as pa
     wl = make_workload("C").subset(range(3), n_sweeps=7)
-    st = make_state(wl)
+    _, st = make_state(wl)
     st.sweep(7, 1)
     e = torch.full((st.graph.slots,), -7, dtype=torch.int32, device="cuda")
     st.record(e)
     obs = st.observables().cpu().numpy()
     got = e.cpu().numpy()
     want = np.zeros_like(got)
-    want[obs[:, 3]] = obs[:, 2]
+    base = st.graph.walker_base
+    sys_of = np.repeat(np.arange(len(base) - 1), np.diff(base))
+    want[base[sys_of] + obs[:, 3]] = obs[:, 2]  # obs[:, 3] is the slot within the system
     assert np.array_equal(got, want)
     assert np.array_equal(obs[:, 0], obs[:, 2])

@@ -46,18 +46,29 @@ __device__ __forceinline__ int find_system(const SysInfo *sys, int n_sys, int64_
 }
 
 // Boundary fields b_k = h_k + sum_{j outside the cell} J_kj s_j of cell c of slice m.
-// A template record is read as two 16-byte words (neighbours; couplings, h,
-// J_tau, level, degree, packed in-cell couplings) and unpacked in registers.
+// In-slice edges between cells join grid neighbours only (checked when the
+// graph is loaded), so every outside neighbour in the slice lies in cell c - L,
+// c + L, c - 1 or c + 1: the four spin words holding those cells, and the
+// words of cell c in the slices before and after, are read once up front and
+// each neighbour's bit is picked from them.  A template record is read as two
+// 16-byte words (neighbours; couplings, h, J_tau, level, degree, packed
+// in-cell couplings) and unpacked in registers.
 __device__ __forceinline__ void boundary_fields(const DevTables &T, const SysInfo &sy, const uint32_t *sp, int m,
-                                                int c, int b[8]) {
-  auto bit = [&](int mm, int q) { return (int)((sp[mm * sy.RS + (q >> 5)] >> (q & 31)) & 1u); };
-  const int M = sy.M;
+                                                int c, int b[8], int32_t jpack[4] = nullptr) {
+  const int M = sy.M, L = sy.grid_L;
   const int mp = m == 0 ? M - 1 : m - 1, mn = m == M - 1 ? 0 : m + 1;
   const bool has_p = M > 1 && (m > 0 || sy.ring), has_n = M > 1 && (m < M - 1 || sy.ring);
+  const int y = c / L, x = c - (c / L) * L;
+  const uint32_t *row = sp + m * sy.RS;
+  const int cu = y > 0 ? c - L : c, cd = y < L - 1 ? c + L : c;
+  const int cl = x > 0 ? c - 1 : c, cr = x < L - 1 ? c + 1 : c;
+  const uint32_t wu = row[cu >> 2], wd = row[cd >> 2], wl = row[cl >> 2], wr = row[cr >> 2];
+  const uint32_t own_shift = (c & 3) * 8;
+  const uint32_t bp = has_p ? (sp[mp * sy.RS + (c >> 2)] >> own_shift) & 0xffu : 0u;
+  const uint32_t bn = has_n ? (sp[mn * sy.RS + (c >> 2)] >> own_shift) & 0xffu : 0u;
   const uint4 *rec = (const uint4 *)(T.tmpl + sy.tmpl0 + c * 8);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int q = c * 8 + k;
     const uint4 lo = rec[2 * k], hi = rec[2 * k + 1];  // lo: nbr[0..7]; hi: J[0..7], h, Jtau, f, deg, jpack
     const int deg = (int)(hi.z >> 24);
     const int jtau = (int)(int8_t)((hi.z >> 8) & 0xffu);
@@ -67,12 +78,15 @@ __device__ __forceinline__ void boundary_fields(const DevTables &T, const SysInf
       if (j < deg) {
         const int nb = (int)(int16_t)((((j < 6) ? lo.z : lo.w) >> (16 * (j & 1))) & 0xffffu);
         const int Jv = (int)(int8_t)((hi.y >> (8 * (j - 4))) & 0xffu);
-        f += Jv * (2 * bit(m, nb) - 1);
+        const int cn = nb >> 3;
+        const uint32_t w = cn == cu ? wu : cn == cd ? wd : cn == cl ? wl : wr;
+        f += Jv * (2 * (int)((w >> (nb & 31)) & 1u) - 1);
       }
     }
-    if (has_p) f += jtau * (2 * bit(mp, q) - 1);
-    if (has_n) f += jtau * (2 * bit(mn, q) - 1);
+    if (has_p) f += jtau * (2 * (int)((bp >> k) & 1u) - 1);
+    if (has_n) f += jtau * (2 * (int)((bn >> k) & 1u) - 1);
     b[k] = f;
+    if (jpack && k < 4) jpack[k] = (int32_t)hi.w;
   }
 }
 
@@ -124,12 +138,15 @@ __device__ __forceinline__ int unit_at(int c) {
 // Row strides are padded by 8 BF16 (16 bytes): the 16 rows that one matrix
 // operand read touches then fall on distinct LDS banks.
 constexpr int kS1 = 40, kS2 = 136;
+// Wavefronts per workgroup: six share one copy of the weights (75 KB of LDS),
+// two workgroups fit a compute unit, three wavefronts per SIMD.
+constexpr int kProposeWaves = 6;
 struct alignas(16) ProposeLds {
   uint16_t W1[128 * kS1];  // [unit][input], inputs padded to 32
   uint16_t W2[128 * kS2];  // [unit][position], positions in unit_at order
   uint16_t W3[16 * kS2];   // [output (8 + 8 zero rows)][position]
   float b1[128], b2[128], b3[16];
-  uint16_t X[4][64 * kS1];  // per wavefront: inputs of its 64 rows, then their logits
+  uint16_t X[kProposeWaves][64 * kS1];  // per wavefront: inputs of its 64 rows, then their logits
 };
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -155,7 +172,7 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                   0, 0);
 }
 
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_waves_per_eu(3)))
     cell_propose_kernel(DevTables T, DevState St, int32_t n_sys, int64_t rows_total, int32_t phase, const float *w,
                         const uint16_t *wb, uint64_t key, int64_t pass_index, uint64_t *moves) {
   __shared__ ProposeLds s;
@@ -180,7 +197,8 @@ __global__ void __launch_bounds__(256, 2)
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, n16 = l & 15, g = l >> 4;
   uint16_t *X = s.X[wv];
   const int64_t tiles = rows_total / 64;  // rows_total is a multiple of 64
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+  for (int64_t tile = (int64_t)blockIdx.x * kProposeWaves + wv; tile < tiles;
+       tile += (int64_t)gridDim.x * kProposeWaves) {
     // ---- this lane's row: locate the cell, boundary fields, input ----
     // a tile lies in one system: its record is read once for the wavefront
     const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
@@ -197,18 +215,17 @@ __global__ void __launch_bounds__(256, 2)
     float beta = 0.f;
     uint8_t *bytep = nullptr;
     uint32_t cur = 0;
-    int jt = 0;  // template index of the cell's first spin
+    int32_t jpack[4] = {0, 0, 0, 0};  // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
     if (valid) {
       r = sy.walker0 + wk;
       ci = T.cells[sy.cl0 + sy.pc[phase] + j];
       const int LL = sy.grid_L * sy.grid_L;
       const int m = ci / LL, c = ci - m * LL;
       const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)wk * sy.WW;
-      boundary_fields(T, sy, sp, m, c, b);
+      boundary_fields(T, sy, sp, m, c, b, jpack);
       bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)wk * sy.WW + m * sy.RS + ((c * 8) >> 5)) + (c & 3);
       cur = *bytep;
       beta = (float)T.beta[sy.slot0 + St.temp_of[r]];
-      jt = sy.tmpl0 + c * 8;
     }
     {
       u32x4 *xr = (u32x4 *)(X + l * kS1);
@@ -240,43 +257,38 @@ __global__ void __launch_bounds__(256, 2)
         h1[ft >> 1][t][(ft & 1) * 2 + 1] = relu_bf2(acc[2], acc[3]);
       }
     }
-    // ---- layer 2 (the next unit tile's weights are read while this one multiplies) ----
-    u32x4 h2[4][4];
-    u32x4 wa[4], wn[4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) wa[kk] = *(const u32x4 *)(s.W2 + n16 * kS2 + kk * 32 + g * 8);
-#pragma unroll
-    for (int ft = 0; ft < 8; ++ft) {
-      if (ft < 7) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) wn[kk] = *(const u32x4 *)(s.W2 + ((ft + 1) * 16 + n16) * kS2 + kk * 32 + g * 8);
-      }
-      f32x4 acc[4];
-      const f32x4 bias = *(const f32x4 *)(s.b2 + ft * 16 + 4 * g);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = bias;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = mfma16(wa[kk], h1[kk][t], acc[t]);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        h2[ft >> 1][t][(ft & 1) * 2] = relu_bf2(acc[t][0], acc[t][1]);
-        h2[ft >> 1][t][(ft & 1) * 2 + 1] = relu_bf2(acc[t][2], acc[t][3]);
-      }
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) wa[kk] = wn[kk];
-    }
-    // ---- layer 3: logits (outputs 8..15 are zero padding) ----
+    // ---- layers 2 and 3: each pair of layer-2 unit tiles (2kk, 2kk + 1) completes
+    // contraction chunk kk of layer 3, which is consumed at once ----
     f32x4 acc3[4];
-    const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));
+    const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));  // outputs 8..15 are zero padding
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc3[t] = bias3;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const u32x4 a = *(const u32x4 *)(s.W3 + n16 * kS2 + kk * 32 + g * 8);
+    for (int kk3 = 0; kk3 < 4; ++kk3) {
+      u32x4 h2[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc3[t] = mfma16(a, h2[kk][t], acc3[t]);
+      for (int half = 0; half < 2; ++half) {
+        const int ft = 2 * kk3 + half;
+        u32x4 wa[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) wa[kk] = *(const u32x4 *)(s.W2 + (ft * 16 + n16) * kS2 + kk * 32 + g * 8);
+        f32x4 acc[4];
+        const f32x4 bias = *(const f32x4 *)(s.b2 + ft * 16 + 4 * g);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = bias;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] = mfma16(wa[kk], h1[kk][t], acc[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          h2[t][half * 2] = relu_bf2(acc[t][0], acc[t][1]);
+          h2[t][half * 2 + 1] = relu_bf2(acc[t][2], acc[t][3]);
+        }
+      }
+      const u32x4 a3 = *(const u32x4 *)(s.W3 + n16 * kS2 + kk3 * 32 + g * 8);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc3[t] = mfma16(a3, h2[t], acc3[t]);
     }
     wave_fence();  // every lane has read its inputs: the region now takes logits
     float *Lg = (float *)X;
@@ -297,11 +309,9 @@ __global__ void __launch_bounds__(256, 2)
       for (int k = 0; k < 8; ++k) lg[k] = Lg[l * 8 + k];
       int jin[16];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int32_t pk = T.tmpl[jt + k].jpack;  // 2J to partners 4..7
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((pk >> (8 * i)) & 0xff)) / 2;
-      }
+        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((jpack[k] >> (8 * i)) & 0xff)) / 2;
       const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
       uint32_t wd[12];
 #pragma unroll
@@ -363,8 +373,8 @@ hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_
                                uint64_t *moves, hipStream_t st) {
   if (rows_total <= 0) return hipSuccess;
   const int64_t tiles = rows_total / 64;
-  const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 512);
-  hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(256), 0, st, t, s, n_sys, rows_total, phase, w, wb, key,
+  const int blocks = (int)std::min<int64_t>((tiles + kProposeWaves - 1) / kProposeWaves, 512);
+  hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(64 * kProposeWaves), 0, st, t, s, n_sys, rows_total, phase, w, wb, key,
                      pass_index, moves);
   return hipGetLastError();
 }

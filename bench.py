@@ -18,22 +18,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak, TFLOP/s
 BYTES_PER_ATTEMPT = 12         # spin r+w 2 B, field r+w 2 B, MT word r+w 8 B
+FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
+# HBM bytes per sweep launch on the throughput workload, from rocprofv3 FETCH_SIZE (x2.00) and
+# WRITE_SIZE (x1.00) scaled against a device copy of known size (sweep kernel unchanged since).
+SWEEP_TRAFFIC_BYTES = {"B": 156.8e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """The oracle on the host's cores over a bounded sample of the same workload."""
+def cpu_baseline(wl, budget_s=15.0):
+    """The oracle on the host's cores over a bounded sample of the same workload:
+    the first systems (at least two per core), every walker, as many sweeps (with a
+    swap round after each) as fit the time budget, at most the workload's own."""
     import oracle
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     nsys = min(len(wl.systems), max(2 * ncores, 8))
-    idx = list(range(nsys))
-    chains = oracle.workload_chains(wl, idx)
-    per_sweep = sum(wl.systems[i].N * wl.systems[i].K for i in idx)
+    chains = oracle.workload_chains(wl, list(range(nsys)))
     t0 = time.perf_counter()
     oracle.run_many(chains, 1, 1, ncores)
     t1 = time.perf_counter() - t0
-    n = max(1, min(int(budget_s / max(t1, 1e-3)), wl.n_sweeps))
+    if t1 * wl.n_sweeps < budget_s:  # the whole run of these systems is short: take more systems
+        nsys = min(len(wl.systems), int(nsys * budget_s / (t1 * wl.n_sweeps)) + 1)
+        chains = oracle.workload_chains(wl, list(range(nsys)))
+        t0 = time.perf_counter()
+        oracle.run_many(chains, 1, 1, ncores)
+        t1 = time.perf_counter() - t0
+    per_sweep = sum(wl.systems[i].N * wl.systems[i].K for i in range(nsys))
+    n = max(1, min(int(budget_s / max(t1, 1e-3)), wl.n_sweeps - 1))
     t0 = time.perf_counter()
     oracle.run_many(chains, n, 1, ncores)
     dt = time.perf_counter() - t0
@@ -41,6 +53,83 @@ def cpu_baseline(wl, budget_s=12.0):
             "kind": "oracle",
             "sample": f"{nsys} of {len(wl.systems)} systems x {wl.systems[0].K} walkers x {n} sweeps "
                       f"(swap every sweep), {dt:.1f} s"}
+
+
+def learned_leg(ess_steps, train_rows=1 << 20):
+    """Learned cell proposal on the 256 x 32-walker, 4,096-spin workload: train the
+    network on the GPU from plain-chain samples, then effective samples per second of
+    the plain chain (sweep + swap round per step) against the learned chain (sweep +
+    swap round + one pass of learned cell moves per step), both from the same state."""
+    import numpy as np
+    import torch
+
+    import paper_1004_0024_amd as pa
+    from paper_1004_0024_amd import learn
+    from gen import make_workload
+    from gen.mlp import initial_params
+
+    wl = make_workload("E")
+    g = pa.Graph(wl.systems)
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    st.sweep(3000, 1)  # burn-in
+    t0 = time.perf_counter()
+    x, y = learn.collect(st, train_rows, snapshots=8, sweeps_between=5)
+    net = pa.Mlp(initial_params(11))
+    net0 = pa.Mlp(initial_params(11))
+    loss0 = float(net.grad_step(x[:4096], y[:4096]).item())
+    losses = np.concatenate([learn.train(net, x, y, batch=4096, epochs=1, lr=lr) for lr in (2e-3, 2e-3, 5e-4)])
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    base = pa.State(g).copy_from(st)
+    # acceptance of one pass, untrained vs trained network, from the same state
+    acc = {}
+    for name, n in (("untrained", net0), ("trained", net)):
+        s2 = pa.State(g).copy_from(base)
+        mv = torch.zeros((g.R, 2), dtype=torch.int64, device="cuda")
+        s2.propose_cells(n, 7, 0, mv)
+        m = mv.sum(0).cpu().numpy()
+        acc[name] = float(m[1]) / float(m[0])
+    # cell-move kernel time: events around passes on the current stream
+    s2 = pa.State(g).copy_from(base)
+    stream = torch.cuda.current_stream()
+    passes = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s2.propose_cells(net, 9, 0)
+    e0.record(stream)
+    for p in range(passes):
+        s2.propose_cells(net, 9, 1 + p)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    # colour classes of the cells: 2, or 4 on a ring of odd length
+    launches = passes * max(4 if (s.ring and s.M % 2 == 1) else 2 for s in wl.systems)
+    launch_ms = e0.elapsed_time(e1) / launches
+    cells_per_pass = sum(s.M * s.L * s.L * s.K for s in wl.systems)
+    flops = FLOPS_PER_CELL * cells_per_pass / (launches / passes)
+    tflops = flops / (launch_ms / 1e3) / 1e12
+    chains = {}
+    for name, n in (("plain", None), ("learned", net)):
+        s2 = pa.State(g).copy_from(base)
+        r = learn.run(s2, ess_steps, n, pass0=1000)
+        e = learn.ess_summary(g, r["e"])
+        chains[name] = {"ms_per_step": r["ms"] / ess_steps, "ess_coldest": e["coldest_total"],
+                        "ess_median_slot": e["median_slot"],
+                        "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3),
+                        "coldest_mean_energy": float(r["e"][:, 31::32].mean())}
+        if "acceptance" in r:
+            chains[name]["cell_acceptance"] = r["acceptance"]
+    return {
+        "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": 3000,
+        "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems",
+        "train": {"rows": int(x.shape[0]), "batch": 4096, "adam_steps": int(len(losses)),
+                  "loss_untrained": loss0, "loss_last": float(losses[-1]), "seconds": train_s},
+        "acceptance_one_pass": acc,
+        "plain": chains["plain"], "learned": chains["learned"],
+        "ess_per_s_learned_over_plain": chains["learned"]["ess_per_s"] / chains["plain"]["ess_per_s"],
+        "roofline": {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
+                     "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,
+                     "cells_per_launch": cells_per_pass / (launches / passes), "traffic": None},
+    }
 
 
 def main():
@@ -53,10 +142,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
+    ap.add_argument("--ess-steps", type=int, default=10000,
+                    help="chain steps per ESS estimate in the learned-proposal leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
-              "(systems shard independently across GPUs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the whole path runs on a single MI355X "
+              "(systems shard independently across GPUs, one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -139,7 +231,8 @@ def main():
                    "spins_per_system": wl.systems[0].N, "sweeps_per_step": n_sw, "swap_every": 1,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": SWEEP_TRAFFIC_BYTES.get(args.config), "traffic_unit": "HBM bytes per launch",
                      "kernel": "sweep_kernel", "kernel_avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_attempt": BYTES_PER_ATTEMPT},
         "wall_s_timed": wall,
@@ -147,6 +240,9 @@ def main():
         "launch_shapes": tuned,
         "sweep_kernel_ms": {"mean": avg_sweep_s * 1e3, "min": min(sweep_ms), "max": max(sweep_ms)},
     }
+    del rep, st
+    if not args.no_learned:
+        out["effective_samples"] = learned_leg(args.ess_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -10,7 +10,12 @@
  *   - MT19937 recurrence and tempering      Sec. 3, Fig. 8
  *   - parallel tempering                    Sec. 1 (named; details are the
  *                                           standard replica-exchange rule)
- * Readings of points the paper leaves open are listed in the design doc.
+ * Points the paper leaves open are settled here as follows: a walker's
+ * initial spin i is the top bit of its generator's i-th output; a flip with
+ * d = s_i h_eff_i <= 0 is taken without comparing (its draw is still consumed);
+ * swap rounds alternate even and odd pairs, each pair consumes one draw of its
+ * system's swap generator, and a swap is accepted when Delta >= 0 or
+ * u 2^-32 < exp(Delta), Delta = (beta_k - beta_k+1)(E_k - E_k+1).
  */
 #include "orc.h"
 

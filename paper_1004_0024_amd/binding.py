@@ -229,6 +229,14 @@ class State:
         _check(lib().ising_init_state(self.graph.handle, C.byref(self._s), _np_ptr(ws), _np_ptr(ss), _stream()))
         return self
 
+    def copy_from(self, other):
+        """Make this state (of the same graph) a copy of `other`: device arrays and counters."""
+        assert other.graph is self.graph
+        for name in self._FIELDS:
+            self.t[name].copy_(other.t[name])
+        self._s.sweeps, self._s.rounds = other._s.sweeps, other._s.rounds
+        return self
+
     def sweep(self, n_sweeps, swap_every=1, record=False):
         import torch
         e = None

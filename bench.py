@@ -27,7 +27,7 @@ SWEEP_TRAFFIC_BYTES = {"B": 156.8e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
 
 
-def cpu_baseline(wl, budget_s=15.0):
+def cpu_baseline(wl, budget_s=20.0):
     """The oracle on the host's cores over a bounded sample of the same workload:
     the first systems (at least two per core), every walker, as many sweeps (with a
     swap round after each) as fit the time budget, at most the workload's own."""
@@ -53,6 +53,37 @@ def cpu_baseline(wl, budget_s=15.0):
             "kind": "oracle",
             "sample": f"{nsys} of {len(wl.systems)} systems x {wl.systems[0].K} walkers x {n} sweeps "
                       f"(swap every sweep), {dt:.1f} s"}
+
+
+def batch_leg(name, n_sweeps, reps=3):
+    """Attempts/s of another workload shape: the launch shapes autotuned, then one
+    captured loop of `n_sweeps` sweeps (each followed by a swap round) replayed
+    `reps` times; HIP events on the replay stream."""
+    import torch
+
+    import paper_1004_0024_amd as pa
+    from gen import make_workload
+
+    wl = make_workload(name)
+    g = pa.Graph(wl.systems)
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    g.autotune(scratch, reps=2)
+    del scratch
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    rep = st.capture(n_sweeps, swap_every=1)
+    rep.launch()
+    rep.stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(rep.stream)
+    for _ in range(reps):
+        rep.launch()
+    e1.record(rep.stream)
+    rep.stream.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": wl.name, "systems": len(wl.systems), "walkers": g.R,
+            "attempts_per_sweep": g.attempts_per_sweep, "sweeps_per_replay": n_sweeps,
+            "buckets": len(g.buckets()), "ms_per_sweep": ms / n_sweeps,
+            "value": g.attempts_per_sweep * n_sweeps / (ms / 1e3), "unit": "spin-flip attempts/s"}
 
 
 def learned_leg(ess_steps, train_rows=1 << 20):
@@ -143,6 +174,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
+    ap.add_argument("--no-batches", action="store_true", help="skip the many-replica and uneven-batch legs")
     ap.add_argument("--ess-steps", type=int, default=10000,
                     help="chain steps per ESS estimate in the learned-proposal leg")
     args = ap.parse_args()
@@ -241,6 +273,8 @@ def main():
         "sweep_kernel_ms": {"mean": avg_sweep_s * 1e3, "min": min(sweep_ms), "max": max(sweep_ms)},
     }
     del rep, st
+    if not args.no_batches:
+        out["other_shapes"] = [batch_leg("C", 20), batch_leg("D", 10)]
     if not args.no_learned:
         out["effective_samples"] = learned_leg(args.ess_steps)
     if not args.no_cpu_baseline:

@@ -386,7 +386,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     int32_t maxw = 0, Kmax = 1;
     for (int32_t s : kv.second) {
       const SysInfo &si = g.sys[s];
-      maxw = std::max(maxw, walker_lds_words(si.S, si.WW, si.fifo_words));
+      maxw = std::max(maxw, walker_lds_words(si.S, si.WW, si.fifo_words, si.RS));
       Kmax = std::max(Kmax, si.K);
     }
     b.walker_words = maxw;

@@ -79,9 +79,10 @@ __host__ __device__ inline int32_t fifo_depth(int32_t f) {
 }
 
 // LDS words of one walker slot: generator ring (+ shadow), uniform queues,
-// spins, threshold row, reduction slots.
-__host__ __device__ inline int32_t walker_lds_words(int32_t S, int32_t WW, int32_t FW) {
-  return gen_ring_words(S) + kMtN + FW + WW + kThrRow + 4;
+// spins (M rows of RS words, with one halo row before and one after), threshold
+// row, reduction slots.
+__host__ __device__ inline int32_t walker_lds_words(int32_t S, int32_t WW, int32_t FW, int32_t RS) {
+  return gen_ring_words(S) + kMtN + FW + WW + 2 * RS + kThrRow + 4;
 }
 
 struct DevTables {

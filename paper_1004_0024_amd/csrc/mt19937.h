@@ -12,10 +12,12 @@ __device__ __forceinline__ uint32_t mt_next_word(uint32_t a, uint32_t b, uint32_
   return c ^ (y >> 1) ^ ((0u - (y & 1u)) & 0x9908b0dfu);
 }
 
+// Tempering.  The two masked steps v ^ ((v << s) & C) are one three-input
+// bit operation each (truth table 0x78: a ^ (b & c), operand order a, b, c).
 __device__ __forceinline__ uint32_t mt_temper(uint32_t v) {
   v ^= v >> 11;
-  v ^= (v << 7) & 0x9d2c5680u;
-  v ^= (v << 15) & 0xefc60000u;
+  v = __builtin_amdgcn_bitop3_b32(v, v << 7, 0x9d2c5680u, 0x78);
+  v = __builtin_amdgcn_bitop3_b32(v, v << 15, 0xefc60000u, 0x78);
   v ^= v >> 18;
   return v;
 }

@@ -24,7 +24,9 @@
 //
 // Data in LDS for the whole launch, per walker:
 //  - spins, one bit each, slice rows of RS words (RS odd when > 1, so rows of
-//    different slices fall in different LDS banks);
+//    different slices fall in different LDS banks); on a ring, a halo row in
+//    front holds a copy of the last slice and one behind a copy of the first,
+//    so the tau neighbours of every slice are the rows just before and after;
 //  - the MT19937 generator ring: word n (counted from the launch's first
 //    window word) in slot (n + delta) mod Zg, chunks of S words aligned to
 //    slot multiples of S, with a copy of the top kMtN slots in front of slot 0
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   const int nw = tile.nw;
   const int tid = threadIdx.x, nthr = blockDim.x;
 
-  // walker slot layout: [shadow | generator ring][queues][spins][thr][acc]
+  // walker slot layout: [shadow | generator ring][queues][halo row, spins, halo row][thr][acc]
   uint32_t *fifo_tab = lds + G * PW;  // [S] shared by the tile's walkers
   auto wbase = [&](int w) { return lds + w * PW; };
 
@@ -88,19 +90,24 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     g[x] = v;
     if (x >= zs) g[x - Zg] = v;
   }
-  for (int i = tid; i < nw * WW; i += nthr) {
-    const int w = i / WW, j = i - w * WW;
-    wbase(w)[ZP + FW + j] = init_mode ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j];
+  const int SWW = WW + 2 * RS;  // spin rows with the two halo rows
+  for (int i = tid; i < nw * SWW; i += nthr) {
+    const int w = i / SWW, j = i - w * SWW;
+    int src = j - RS;  // halo rows: copies of the last and the first slice (ring), else zero
+    if (src < 0) src = RING ? src + WW : -1;
+    else if (src >= WW) src = RING ? src - WW : -1;
+    wbase(w)[ZP + FW + j] =
+        (init_mode || src < 0) ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + src];
   }
   if (!init_mode) {
     for (int i = tid; i < nw * kThrRow; i += nthr) {
       const int w = i / kThrRow, j = i - w * kThrRow;
       const int slot = St.temp_of[sy.walker0 + tile.w0 + w];
-      wbase(w)[ZP + FW + WW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
+      wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
     }
   }
   for (int i = tid; i < S; i += nthr) fifo_tab[i] = T.fifo[sy.tmpl0 + i];
-  for (int i = tid; i < nw * 4; i += nthr) wbase(i / 4)[ZP + FW + WW + kThrRow + (i & 3)] = 0u;
+  for (int i = tid; i < nw * 4; i += nthr) wbase(i / 4)[ZP + FW + SWW + kThrRow + (i & 3)] = 0u;
 
   // ---- this thread's walker and columns ----
   const int gw = tid / TPW, t = tid - gw * TPW;
@@ -108,8 +115,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   uint32_t *wb = wbase(live ? gw : 0);
   uint32_t *gring = wb + kMtN;  // logical slot 0
   uint32_t *fq = wb + ZP;
-  uint32_t *sp = fq + FW;
-  const uint32_t *thw = sp + WW;
+  uint32_t *sp = fq + FW + RS;  // row 0 (halo rows at sp - RS and sp + WW)
+  const uint32_t *thw = sp + WW + RS;
   int32_t *acc = (int32_t *)(thw + kThrRow);
 
   int qo[CPT], qb[CPT], base[CPT], jt[CPT], f[CPT], jpack[CPT], fb[CPT], fmask[CPT];
@@ -140,7 +147,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
       sumJ += ts.J[(CELL ? 4 : 0) + j];
     }
     jt[c] = ts.Jtau;
-    f[c] = ts.f;
+    f[c] = col[c] ? (int)ts.f : (1 << 24);  // a column without a spin is never active
     // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms: the constant part is `base`.
     base[c] = (int)ts.h - sumJ - (RING ? 2 * (int)ts.Jtau : 0);
     const uint32_t fw = T.fifo[sy.tmpl0 + qq0];
@@ -149,11 +156,27 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   }
 
   // Generator: chain heads j < min(S, 227) go round-robin to the walker's
-  // threads; a head makes words j, j+227, j+454 (< S) of each chunk.
+  // threads (head h of thread t is j = t + h*TPW; TPW*CPT >= S, so h < CPT);
+  // a head makes words j, j+227, j+454 (< S) of each chunk.  The uniform
+  // queue of each word's column is resolved once, into registers.
   const int heads = S < kMtLag ? S : kMtLag;
+  int gqb[CPT][3], gqm[CPT][3];
+#pragma unroll
+  for (int h = 0; h < CPT; ++h)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int o = t + h * TPW + s * kMtLag;
+      const bool ok = live && t + h * TPW < heads && o < S;
+      const uint32_t fw = ok ? T.fifo[sy.tmpl0 + o] : 0u;
+      gqb[h][s] = (int)(fw >> 8);
+      gqm[h][s] = (1 << (fw & 0xff)) - 1;
+    }
   auto gen_chunk = [&](int gslot, int chunk) {
     if (!live) return;
-    for (int j = t; j < heads; j += TPW) {
+#pragma unroll
+    for (int h = 0; h < CPT; ++h) {
+      const int j = t + h * TPW;
+      if (j >= heads) break;
       uint32_t a[3], b[3];
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
@@ -172,8 +195,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
           prev = mt_next_word(a[s], b[s], prev);
           gring[x] = prev;
           if (x >= zs) gring[x - Zg] = prev;
-          const uint32_t fw = fifo_tab[o];
-          fq[(int)(fw >> 8) + (chunk & ((1 << (fw & 0xff)) - 1))] = prev;
+          fq[gqb[h][s] + (chunk & gqm[h][s])] = prev;
         }
       }
     }
@@ -186,8 +208,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   __syncthreads();
 
   int gslot = c0 * S;  // generator slot of the next chunk
-  int dE = 0, nfl = 0;
-  uint32_t st_steps = 0, st_flip = 0;
+  int dE = 0, nfl = 0;  // per lane: sum of d over flips (the cost changes by 2d), flips
+  uint32_t st_steps = 0, st_flip = 0, nfl_w = 0;  // per wavefront
 
   gen_chunk(gslot, 0);
   gslot = advance(gslot);
@@ -211,22 +233,23 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
   } else {
     const int levels = M + F - 1;
-    const int last_row = (M - 1) * RS;
+    const bool wave_walker = TPW >= 64;  // a wavefront's lanes belong to one walker
     for (int sw = 0; sw < n_sweeps; ++sw) {
       const int chunk0 = sw * M;
       for (int lv = 0; lv < levels; ++lv) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
           const int m = lv - f[c];
-          const bool active = col[c] && m >= 0 && m < M;
-          bool flip = false;
-          if (active) {
-            const int rc = (int)__umul24((unsigned)m, (unsigned)RS) + qo[c];
-            const int rpp = m == 0 ? last_row + qo[c] : rc - RS;
-            const int rnn = m == M - 1 ? qo[c] : rc + RS;
+          const bool active = (unsigned)m < (unsigned)M;
+          // Wavefronts with no active lane skip the column; inside, inactive
+          // lanes compute on row 0 (in bounds) and their result is dropped.
+          if (__builtin_amdgcn_ballot_w64(active) != 0ull) {
+            ++st_steps;
+            const int mm = active ? m : 0;
+            const int rc = (int)__umul24((unsigned)mm, (unsigned)RS) + qo[c];
             uint32_t *own_p = sp + rc;
             const uint32_t own = *own_p;
-            const uint32_t u0 = fq[fb[c] + ((chunk0 + m) & fmask[c])];
+            const uint32_t u0 = fq[fb[c] + ((chunk0 + mm) & fmask[c])];
             int hs = base[c];
             if (CELL) {
               const uint32_t nib = __builtin_amdgcn_ubfe(own, (unsigned)((qb[c] & ~3) ^ 4), 4u);
@@ -236,26 +259,32 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 #pragma unroll
             for (int j = 0; j < NX; ++j)
               hs += __builtin_amdgcn_sbfe((int)own_p[xoff[c][j]], (unsigned)xbit[c][j], 1u) & xj2[c][j];
-            const int bp = (int)__builtin_amdgcn_ubfe(sp[rpp], (unsigned)qb[c], 1u);
-            const int bn = (int)__builtin_amdgcn_ubfe(sp[rnn], (unsigned)qb[c], 1u);
+            const int bp = (int)__builtin_amdgcn_ubfe(own_p[-RS], (unsigned)qb[c], 1u);
+            const int bn = (int)__builtin_amdgcn_ubfe(own_p[RS], (unsigned)qb[c], 1u);
             if (RING) {
               hs += 2 * jt[c] * (bp + bn);
             } else {
-              const int jp = m > 0 ? jt[c] : 0, jn = m < M - 1 ? jt[c] : 0;
+              const int jp = mm > 0 ? jt[c] : 0, jn = mm < M - 1 ? jt[c] : 0;
               hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
             }
             const int sb = (int)__builtin_amdgcn_ubfe(own, (unsigned)qb[c], 1u);
             const int d = sb ? hs : -hs;  // s_i * h_eff_i; flipping costs 2d
             const uint32_t u = mt_temper(u0);
-            flip = u <= thw[d > 0 ? d : 0];
+            const bool flip = active & (u <= thw[d > 0 ? d : 0]);
+            const uint64_t fl = __builtin_amdgcn_ballot_w64(flip);
+            st_flip += fl != 0ull;
+            if (wave_walker) nfl_w += (uint32_t)__builtin_popcountll(fl);
+            else nfl += flip ? 1 : 0;
+            dE += flip ? d : 0;
             if (flip) {
-              atomicXor(own_p, 1u << qb[c]);
-              dE += 2 * d;
-              ++nfl;
+              const uint32_t bit = 1u << qb[c];
+              atomicXor(own_p, bit);
+              if (RING) {  // keep the halo copy of the first / last slice
+                if (mm == 0) atomicXor(own_p + WW, bit);
+                if (mm == M - 1) atomicXor(own_p - WW, bit);
+              }
             }
           }
-          st_steps += __ballot(active) != 0ull;
-          st_flip += __ballot(flip) != 0ull;
         }
         if (lv + 1 < M) {
           gen_chunk(gslot, chunk0 + lv + 1);
@@ -271,18 +300,20 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 
   // ---- write back ----
   if (live && !init_mode) {
-    atomicAdd(&acc[0], dE);
-    atomicAdd(&acc[1], nfl);
-    // wavefront statistics go to the walker of the wavefront's first lane
+    atomicAdd(&acc[0], 2 * dE);
+    if (nfl) atomicAdd(&acc[1], nfl);
+    // wavefront statistics (and, when a wavefront is one walker's, its flip
+    // count) go to the walker of the wavefront's first lane
     if ((tid & 63) == 0) {
       atomicAdd(&acc[2], (int)st_steps);
       atomicAdd(&acc[3], (int)st_flip);
+      if (nfl_w) atomicAdd(&acc[1], (int)nfl_w);
     }
   }
   __syncthreads();
   for (int i = tid; i < nw * WW; i += nthr) {
     const int w = i / WW, j = i - w * WW;
-    St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j] = wbase(w)[ZP + FW + j];
+    St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j] = wbase(w)[ZP + FW + RS + j];
   }
   const long long consumed = init_mode ? (long long)M * S : (long long)n_sweeps * M * S;
   for (int i = tid; i < nw * kMtN; i += nthr) {
@@ -292,7 +323,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   }
   if (!init_mode && tid < nw) {
     const int r = sy.walker0 + tile.w0 + tid;
-    const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + WW + kThrRow);
+    const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + SWW + kThrRow);
     St.energy[r] += a[0];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
     St.wsteps[2 * (size_t)r] += (unsigned long long)(uint32_t)a[2];

@@ -174,16 +174,34 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
   }
   if (F > 255) return fail(ISING_E_RANGE, "system %d: schedule depth %d exceeds 255", idx, F);
   out.F = F;
+  // Uniform queues.  Slot k of column q's queue is word base(q) + 64 k: a
+  // queue lives in one LDS bank.  The columns of a 64-column group (the lanes
+  // of one wavefront) take 64 different banks, bank (q + r_w) mod 64 with a
+  // rotation r_w per group chosen so that the banks' stacks stay even; a
+  // wavefront's reads and writes of the queues then never conflict.
   out.fifo.assign(S, 0);
-  int32_t fw = 0;
-  for (int32_t q = 0; q < S; ++q) {
-    const int32_t dq = fifo_depth(f[q]);
-    int32_t lg = 0;
-    while ((1 << lg) < dq) ++lg;
-    out.fifo[q] = ((uint32_t)fw << 8) | (uint32_t)lg;
-    fw += dq;
+  {
+    int32_t height[64] = {0};
+    for (int32_t g0 = 0; g0 < S; g0 += 64) {
+      int32_t best_r = 0, best_h = INT32_MAX;
+      for (int32_t r = 0; r < 64; ++r) {
+        int32_t hmax = 0;
+        for (int32_t l = 0; l < 64 && g0 + l < S; ++l)
+          hmax = std::max(hmax, height[(l + r) & 63] + fifo_depth(f[g0 + l]));
+        if (hmax < best_h) best_h = hmax, best_r = r;
+      }
+      for (int32_t l = 0; l < 64 && g0 + l < S; ++l) {
+        const int32_t q = g0 + l, b = (l + best_r) & 63, dq = fifo_depth(f[q]);
+        int32_t lg = 0;
+        while ((1 << lg) < dq) ++lg;
+        out.fifo[q] = ((uint32_t)(height[b] * 64 + b) << 8) | (uint32_t)lg;
+        height[b] += dq;
+      }
+    }
+    int32_t hmax = 0;
+    for (int32_t b = 0; b < 64; ++b) hmax = std::max(hmax, height[b]);
+    out.FW = hmax * 64;
   }
-  out.FW = fw;
   // Grid of 8-spin cells (cell moves): S = 8 L^2, cell templates, and every
   // in-slice edge between two cells joins grid neighbours; then cells coloured
   // (y + x + m) mod 2 share no edge (on a ring of odd length the last slice
@@ -294,7 +312,7 @@ static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
   if (G < 1) return fail(ISING_E_RANGE, "G must be >= 1");
   G = std::min(G, Kmax);
   if ((int64_t)G * tpw > 1024) return fail(ISING_E_RANGE, "G*tpw exceeds 1024 threads");
-  const size_t lds = ((size_t)G * b.walker_words + b.S) * 4;
+  const size_t lds = (size_t)G * b.walker_words * 4;
   if (lds > 160 * 1024) return fail(ISING_E_RANGE, "launch shape needs %zu bytes of LDS (> 160 KiB)", lds);
   b.tpw = tpw;
   b.cpt = cpt;

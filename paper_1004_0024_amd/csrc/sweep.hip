@@ -34,7 +34,9 @@
 //  - one uniform queue per template column: chunk g (the uniforms of slice
 //    m = g mod M of sweep g / M) is generated one level before its first
 //    consumer and each word is also copied to the queue of its column, slot
-//    g mod depth, where it waits until the column reaches that slice;
+//    g mod depth, where it waits until the column reaches that slice (slot k
+//    of a queue is 64 words after slot k - 1, so a queue sits in one bank and
+//    the 64 columns of a wavefront use 64 different banks);
 //  - the walker's threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1.
 // The local field of a spin is pulled from its neighbours' bits when the spin
 // is visited (no field array, no conflicting neighbour updates).  For cell
@@ -72,7 +74,6 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   const int tid = threadIdx.x, nthr = blockDim.x;
 
   // walker slot layout: [shadow | generator ring][queues][halo row, spins, halo row][thr][acc]
-  uint32_t *fifo_tab = lds + G * PW;  // [S] shared by the tile's walkers
   auto wbase = [&](int w) { return lds + w * PW; };
 
   const int delta = (S - (kMtN % S)) % S;  // chunk-aligned slots
@@ -106,7 +107,6 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
       wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
     }
   }
-  for (int i = tid; i < S; i += nthr) fifo_tab[i] = T.fifo[sy.tmpl0 + i];
   for (int i = tid; i < nw * 4; i += nthr) wbase(i / 4)[ZP + FW + SWW + kThrRow + (i & 3)] = 0u;
 
   // ---- this thread's walker and columns ----
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
           prev = mt_next_word(a[s], b[s], prev);
           gring[x] = prev;
           if (x >= zs) gring[x - Zg] = prev;
-          fq[gqb[h][s] + (chunk & gqm[h][s])] = prev;
+          fq[gqb[h][s] + ((chunk & gqm[h][s]) << 6)] = prev;
         }
       }
     }
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         if (col[c]) {
-          const uint32_t u = mt_temper(fq[fb[c] + (m & fmask[c])]);
+          const uint32_t u = mt_temper(fq[fb[c] + ((m & fmask[c]) << 6)]);
           if (u >> 31) atomicOr(sp + m * RS + qo[c], 1u << qb[c]);
         }
       }
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             const int rc = (int)__umul24((unsigned)mm, (unsigned)RS) + qo[c];
             uint32_t *own_p = sp + rc;
             const uint32_t own = *own_p;
-            const uint32_t u0 = fq[fb[c] + ((chunk0 + mm) & fmask[c])];
+            const uint32_t u0 = fq[fb[c] + (((chunk0 + mm) & fmask[c]) << 6)];
             int hs = base[c];
             if (CELL) {
               const uint32_t nib = __builtin_amdgcn_ubfe(own, (unsigned)((qb[c] & ~3) ^ 4), 4u);

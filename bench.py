@@ -23,7 +23,7 @@ BYTES_PER_ATTEMPT = 12         # spin r+w 2 B, field r+w 2 B, MT word r+w 8 B
 FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
 # HBM bytes per sweep launch on the throughput workload, from rocprofv3 FETCH_SIZE (x2.00) and
 # WRITE_SIZE (x1.00) scaled against a device copy of known size (sweep kernel unchanged since).
-SWEEP_TRAFFIC_BYTES = {"B": 156.8e6}
+SWEEP_TRAFFIC_BYTES = {"B": 157.0e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
 
 

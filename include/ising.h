@@ -230,10 +230,12 @@ int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *
  * W2[128][128], b2[128], W3[8][128], b3[8].                                   */
 #define ISING_MLP_PARAMS 19848
 #define ISING_MLP_PACKED 43008 /* uint16 words of the packed BF16 copies */
+#define ISING_MLP_PARTS 128    /* partial gradients of one step (one per workgroup, at most) */
 typedef struct {
   float *w;       /* [ISING_MLP_PARAMS] FP32 master weights (device) */
   float *m, *v;   /* [ISING_MLP_PARAMS] Adam moments (device) */
   float *grad;    /* [ISING_MLP_PARAMS] gradient (device, written by ising_mlp_grad) */
+  float *part;    /* [ISING_MLP_PARTS][ISING_MLP_PARAMS + 1] scratch of ising_mlp_grad (device) */
   uint16_t *wb;   /* [ISING_MLP_PACKED] BF16 copies read by the kernels (device) */
   int64_t step;   /* host: Adam steps done */
 } ising_mlp;
@@ -243,8 +245,10 @@ int32_t ising_mlp_pack(ising_mlp *net, void *stream);
 /* logits[n][8] (device) of inputs x[n][17] (device FP32). */
 int32_t ising_mlp_forward(const ising_mlp *net, const float *x, int32_t n, float *logits, void *stream);
 /* net->grad = gradient of mean_r -log q(y_r | x_r), y[r] (device bytes) bit k
- * set when cell spin k is +1; *loss (device, nullable) = that mean.  One
- * workgroup, deterministic. */
+ * set when cell spin k is +1; *loss (device, nullable) = that mean.  Up to
+ * ISING_MLP_PARTS workgroups each take every P-th 32-row tile and write a
+ * partial gradient to net->part; the partials are then added in order, so the
+ * result depends only on the batch (bitwise reproducible). */
 int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n, float *loss,
                        void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with net->grad, then repack. */

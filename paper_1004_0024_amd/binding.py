@@ -344,10 +344,10 @@ class Replay:
 
 class MlpStruct(C.Structure):
     _fields_ = [("w", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("grad", C.c_void_p),
-                ("wb", C.c_void_p), ("step", C.c_int64)]
+                ("part", C.c_void_p), ("wb", C.c_void_p), ("step", C.c_int64)]
 
 
-MLP_PARAMS, MLP_PACKED = 19848, 43008
+MLP_PARAMS, MLP_PACKED, MLP_PARTS = 19848, 43008, 128
 
 
 class Mlp:
@@ -361,9 +361,10 @@ class Mlp:
         self.m = torch.zeros_like(self.w)
         self.v = torch.zeros_like(self.w)
         self.grad = torch.zeros_like(self.w)
+        self.part = torch.zeros(MLP_PARTS * (MLP_PARAMS + 1), dtype=torch.float32, device=device)
         self.wb = torch.zeros(MLP_PACKED, dtype=torch.int16, device=device)
         self._s = MlpStruct(self.w.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.grad.data_ptr(),
-                            self.wb.data_ptr(), 0)
+                            self.part.data_ptr(), self.wb.data_ptr(), 0)
         _check(lib().ising_mlp_pack(C.byref(self._s), _stream()))
 
     def forward(self, x):

@@ -868,7 +868,7 @@ extern "C" int32_t ising_observables(const ising_graph *g, const ising_state *st
 // Learned cell proposal: network entry points
 // ---------------------------------------------------------------------------
 static int32_t check_mlp(const ising_mlp *net) {
-  if (!net || !net->w || !net->m || !net->v || !net->grad || !net->wb)
+  if (!net || !net->w || !net->m || !net->v || !net->grad || !net->part || !net->wb)
     return fail(ISING_E_INVAL, "mlp: NULL buffer");
   return ISING_OK;
 }
@@ -894,7 +894,7 @@ extern "C" int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const ui
   int32_t rc = check_mlp(net);
   if (rc) return rc;
   if (n < 1 || !x || !y) return fail(ISING_E_INVAL, "mlp_grad: bad arguments");
-  HIP_TRY(launch_mlp_grad(net->w, net->wb, x, y, n, net->grad, loss, (hipStream_t)stream), "mlp grad");
+  HIP_TRY(launch_mlp_grad(net->w, net->wb, x, y, n, net->part, net->grad, loss, (hipStream_t)stream), "mlp grad");
   return ISING_OK;
 }
 

@@ -21,6 +21,7 @@ constexpr int kPW3 = kPW2 + 128 * 128;
 constexpr int kPW3T = kPW3 + 16 * 128;
 constexpr int kPW2T = kPW3T + 128 * 32;
 constexpr int kPackEnd = kPW2T + 128 * 128;  // 43,008
+constexpr int kMlpParts = 128;  // most workgroups of one gradient step (partial gradients)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -41,8 +42,9 @@ __device__ __forceinline__ void wave_fence() {
 hipError_t launch_mlp_pack(const float *w, uint16_t *wb, hipStream_t st);
 hipError_t launch_mlp_forward(const float *w, const uint16_t *wb, const float *x, int32_t n, float *logits,
                               hipStream_t st);
+int mlp_grad_parts(int32_t n);
 hipError_t launch_mlp_grad(const float *w, const uint16_t *wb, const float *x, const uint8_t *y, int32_t n,
-                           float *grad, float *loss, hipStream_t st);
+                           float *part, float *grad, float *loss, hipStream_t st);
 hipError_t launch_adam(float *w, float *m, float *v, const float *g, int32_t n, float lr, float b1, float b2,
                        float eps, int64_t t, hipStream_t st);
 

@@ -141,21 +141,30 @@ hipError_t launch_mlp_forward(const float *w, const uint16_t *wb, const float *x
   return hipGetLastError();
 }
 
-// ---- training: forward + backward of a batch in one workgroup ----------------
+// ---- training: forward + backward, partial gradients per workgroup ----------
+// Workgroup p of P takes the 32-row tiles p, p + P, p + 2P, ... of the batch and
+// writes the gradient of its rows (and its loss sum) to part[p]; a second
+// kernel adds the P partials in order.  No atomics: every sum has one owner
+// and a fixed order, so the result depends only on the batch.
 struct alignas(16) GradLds {
   uint16_t W1[128 * 32], W2[128 * 128], W3[16 * 128], W3T[128 * 32], W2T[128 * 128];
   uint16_t X[32 * 32], XT[32 * 32], H1[32 * 128], H1T[128 * 32], H2[32 * 128], H2T[128 * 32];
   uint16_t DL[32 * 32], DLT[16 * 32], DZ2[32 * 128], DZ2T[128 * 32], DZ1T[128 * 32];
   float b1[128], b2[128], b3[16];
-  float db1[128], db2[128], db3[16], loss;
+  float db1[128], db2[128], db3w[2][16], lossw[2];
 };
 
 __device__ __forceinline__ float log_sigmoid(float v) { return fminf(v, 0.f) - log1pf(expf(-fabsf(v))); }
 
-// grad = d/dparams of mean_rows -log q(y | x); loss[0] = that mean.  y[r] bit k
-// set means cell spin k is +1.  One workgroup of 256 threads, 32-row tiles.
+// Sum over the four 16-lane groups of a wavefront (lanes l, l+16, l+32, l+48).
+__device__ __forceinline__ float sum_groups(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uint16_t *wb, const float *x,
-                                                       const uint8_t *y, int32_t n, float *grad, float *loss) {
+                                                       const uint8_t *y, int32_t n, float *part) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds_raw[];
   GradLds &s = *reinterpret_cast<GradLds *>(lds_raw);
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
@@ -175,11 +184,9 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
     s.db1[i] = 0.f;
     s.db2[i] = 0.f;
   }
-  if (tid < 16) {
-    s.b3[tid] = tid < kOut ? w[kOB3 + tid] : 0.f;
-    s.db3[tid] = 0.f;
-  }
-  if (tid == 0) s.loss = 0.f;
+  if (tid < 16) s.b3[tid] = tid < kOut ? w[kOB3 + tid] : 0.f;
+  if (tid < 32) s.db3w[tid >> 4][tid & 15] = 0.f;
+  if (tid < 2) s.lossw[tid] = 0.f;
   for (int i = tid; i < 32 * 32; i += 256) s.DL[i] = 0;
   for (int i = tid; i < 16 * 32; i += 256) s.DLT[i] = 0;
   f32x4 gW3[2], gW2[16], gW1[4];
@@ -189,7 +196,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
   const float inv_n = 1.f / (float)n;
   __syncthreads();
 
-  for (int r0 = 0; r0 < n; r0 += 32) {
+  for (int r0 = blockIdx.x * 32; r0 < n; r0 += gridDim.x * 32) {
     // inputs, both layouts
     for (int e = tid; e < 32 * 32; e += 256) {
       const int r = e >> 5, c = e & 31;
@@ -231,40 +238,46 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
         }
       }
     __syncthreads();
-    // layer 3 and the loss gradient dl = (sigmoid(l) - y) / n
+    // layer 3 and the loss gradient dl = (sigmoid(l) - y) / n; wave wv < 2 owns rows 16wv ..
     if (wv < 2) {
       const int rg = wv;
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc = mma(s.H2 + rg * 16 * 128 + kk * 32, 128, s.W3 + kk * 32, 128, acc);
-      if (col16 < kOut) {
+      float dsum = 0.f, lsum = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = rg * 16 + row4 + j;
-          float dl = 0.f;
-          if (r0 + r < n) {
-            const float lg = acc[j] + s.b3[col16];
-            const float yk = (float)((y[r0 + r] >> col16) & 1u);
-            dl = (1.f / (1.f + expf(-lg)) - yk) * inv_n;
-            atomicAdd(&s.loss, -(yk > 0.f ? log_sigmoid(lg) : log_sigmoid(-lg)));
-            atomicAdd(&s.db3[col16], dl);
-          }
+      for (int j = 0; j < 4; ++j) {
+        const int r = rg * 16 + row4 + j;
+        float dl = 0.f;
+        if (col16 < kOut && r0 + r < n) {
+          const float lg = acc[j] + s.b3[col16];
+          const float yk = (float)((y[r0 + r] >> col16) & 1u);
+          dl = (1.f / (1.f + expf(-lg)) - yk) * inv_n;
+          lsum -= yk > 0.f ? log_sigmoid(lg) : log_sigmoid(-lg);
+          dsum += dl;
+        }
+        if (col16 < kOut) {
           const uint16_t v = f2bf(dl);
           s.DL[r * 32 + col16] = v;
           s.DLT[col16 * 32 + r] = v;
         }
       }
+      dsum = sum_groups(dsum);
+      for (int off = 1; off < 16; off <<= 1) lsum += __shfl_xor(lsum, off);
+      lsum = sum_groups(lsum);
+      if (l < 16) s.db3w[wv][l] += dsum;
+      if (l == 0) s.lossw[wv] += lsum;
     }
     __syncthreads();
     // dW3 += dl^T H2 (wave: column tiles 2wv, 2wv+1); dZ2 = (dl W3) * [H2 > 0]
     for (int cc = 0; cc < 2; ++cc) gW3[cc] = mma(s.DLT, 32, s.H2T + (2 * wv + cc) * 16 * 32, 32, gW3[cc]);
-    for (int rg = 0; rg < 2; ++rg)
-      for (int cc = 0; cc < 2; ++cc) {
-        const int ct = 2 * wv + cc;
+    for (int cc = 0; cc < 2; ++cc) {
+      const int ct = 2 * wv + cc;
+      const int c = ct * 16 + col16;
+      float bsum = 0.f;
+      for (int rg = 0; rg < 2; ++rg) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma(s.DL + rg * 16 * 32, 32, s.W3T + ct * 16 * 32, 32, acc);
-        const int c = ct * 16 + col16;
-        float bsum = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int r = rg * 16 + row4 + j;
@@ -274,22 +287,24 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
           s.DZ2T[c * 32 + r] = v;
           bsum += bf2f(v);
         }
-        atomicAdd(&s.db2[c], bsum);
       }
+      bsum = sum_groups(bsum);
+      if (l < 16) s.db2[c] += bsum;  // column c belongs to this wavefront only
+    }
     __syncthreads();
     // dW2 += dZ2^T H1 (wave: row tiles 2wv, 2wv+1 of dW2); dZ1 = (dZ2 W2) * [H1 > 0]
     for (int rr = 0; rr < 2; ++rr)
       for (int ct = 0; ct < 8; ++ct)
         gW2[rr * 8 + ct] = mma(s.DZ2T + (2 * wv + rr) * 16 * 32, 32, s.H1T + ct * 16 * 32, 32, gW2[rr * 8 + ct]);
-    for (int rg = 0; rg < 2; ++rg)
-      for (int cc = 0; cc < 2; ++cc) {
-        const int ct = 2 * wv + cc;
+    for (int cc = 0; cc < 2; ++cc) {
+      const int ct = 2 * wv + cc;
+      const int c = ct * 16 + col16;
+      float bsum = 0.f;
+      for (int rg = 0; rg < 2; ++rg) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
           acc = mma(s.DZ2 + rg * 16 * 128 + kk * 32, 128, s.W2T + ct * 16 * 128 + kk * 32, 128, acc);
-        const int c = ct * 16 + col16;
-        float bsum = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int r = rg * 16 + row4 + j;
@@ -298,8 +313,10 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
           s.DZ1T[c * 32 + r] = v;
           bsum += bf2f(v);
         }
-        atomicAdd(&s.db1[c], bsum);
       }
+      bsum = sum_groups(bsum);
+      if (l < 16) s.db1[c] += bsum;
+    }
     __syncthreads();
     // dW1 += dZ1^T X (wave: row tiles 2wv, 2wv+1 of dW1, both column tiles)
     for (int rr = 0; rr < 2; ++rr)
@@ -307,40 +324,65 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(const float *w, const uin
         gW1[rr * 2 + ct] = mma(s.DZ1T + (2 * wv + rr) * 16 * 32, 32, s.XT + ct * 16 * 32, 32, gW1[rr * 2 + ct]);
     __syncthreads();
   }
-  // ---- write the gradient ----
+  // ---- this workgroup's partial gradient and loss sum ----
+  float *g = part + (size_t)blockIdx.x * (kNParams + 1);
   for (int cc = 0; cc < 2; ++cc) {
     const int c = (2 * wv + cc) * 16 + col16;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = row4 + j;  // output feature of layer 3 (rows 8..15 are padding)
-      if (r < kOut) grad[kOW3 + r * 128 + c] = gW3[cc][j];
+      if (r < kOut) g[kOW3 + r * 128 + c] = gW3[cc][j];
     }
   }
   for (int rr = 0; rr < 2; ++rr)
     for (int ct = 0; ct < 8; ++ct) {
       const int c = ct * 16 + col16;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) grad[kOW2 + ((2 * wv + rr) * 16 + row4 + j) * 128 + c] = gW2[rr * 8 + ct][j];
+      for (int j = 0; j < 4; ++j) g[kOW2 + ((2 * wv + rr) * 16 + row4 + j) * 128 + c] = gW2[rr * 8 + ct][j];
     }
   for (int rr = 0; rr < 2; ++rr)
     for (int ct = 0; ct < 2; ++ct) {
       const int c = ct * 16 + col16;
       if (c < kIn) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) grad[kOW1 + ((2 * wv + rr) * 16 + row4 + j) * kIn + c] = gW1[rr * 2 + ct][j];
+        for (int j = 0; j < 4; ++j) g[kOW1 + ((2 * wv + rr) * 16 + row4 + j) * kIn + c] = gW1[rr * 2 + ct][j];
       }
     }
   __syncthreads();
   for (int i = tid; i < 128; i += 256) {
-    grad[kOB1 + i] = s.db1[i];
-    grad[kOB2 + i] = s.db2[i];
+    g[kOB1 + i] = s.db1[i];
+    g[kOB2 + i] = s.db2[i];
   }
-  if (tid < kOut) grad[kOB3 + tid] = s.db3[tid];
-  if (tid == 0 && loss) loss[0] = s.loss * inv_n;
+  if (tid < kOut) g[kOB3 + tid] = s.db3w[0][tid] + s.db3w[1][tid];
+  if (tid == 0) g[kNParams] = s.lossw[0] + s.lossw[1];
 }
 
+// grad[i] = sum over p of part[p][i]; loss = (sum of loss sums) / n.  Block:
+// 64 entries x 4 lanes; lane group k adds parts p = k, k + 4, ... in order,
+// then the four sums are added k = 0..3.  The order depends only on P.
+__global__ void __launch_bounds__(256) mlp_reduce_kernel(const float *part, int32_t P, int32_t n, float *grad,
+                                                         float *loss) {
+  __shared__ float red[4][64];
+  const int k = threadIdx.x >> 6, e = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + e;
+  float v = 0.f;
+  if (i <= kNParams) {
+#pragma unroll 8
+    for (int p = k; p < P; p += 4) v += part[(size_t)p * (kNParams + 1) + i];
+  }
+  red[k][e] = v;
+  __syncthreads();
+  if (k == 0 && i <= kNParams) {
+    const float t = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    if (i < kNParams) grad[i] = t;
+    else if (loss) loss[0] = t / (float)n;
+  }
+}
+
+int mlp_grad_parts(int32_t n) { return std::max(1, std::min(kMlpParts, (n + 31) / 32)); }
+
 hipError_t launch_mlp_grad(const float *w, const uint16_t *wb, const float *x, const uint8_t *y, int32_t n,
-                           float *grad, float *loss, hipStream_t st) {
+                           float *part, float *grad, float *loss, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void *)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -348,7 +390,9 @@ hipError_t launch_mlp_grad(const float *w, const uint16_t *wb, const float *x, c
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(1), dim3(256), sizeof(GradLds), st, w, wb, x, y, n, grad, loss);
+  const int P = mlp_grad_parts(n);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(P), dim3(256), sizeof(GradLds), st, w, wb, x, y, n, part);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kNParams + 1 + 63) / 64), dim3(256), 0, st, part, P, n, grad, loss);
   return hipGetLastError();
 }
 

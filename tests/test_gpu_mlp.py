@@ -110,3 +110,25 @@ def test_training_reduces_loss():
     last = float(net.grad_step(xt, yt).item())
     say("loss", first, "->", last)
     assert last < 0.5 * first
+
+
+@pytest.mark.parametrize("n", [4113, 9000])
+def test_gradient_many_workgroups_reproducible(n):
+    """More tiles than partial-gradient slots (some workgroups take several tiles):
+    the gradient matches the mirror and two calls agree bit for bit."""
+    import torch
+    import paper_1004_0024_amd as pa
+    p = _params(9)
+    x, y, yb = _data(n, 10)
+    net = pa.Mlp(p)
+    xt, yt = torch.from_numpy(x).float().cuda(), torch.from_numpy(yb).cuda()
+    l1 = net.grad_step(xt, yt).clone()
+    g1 = net.grad.clone()
+    l2 = net.grad_step(xt, yt)
+    assert torch.equal(g1, net.grad) and torch.equal(l1, l2)
+    g = g1.cpu().numpy().astype(np.float64)
+    pp = L.unpack(p)
+    l16, c16 = L.forward_bf16(pp, x)
+    g16 = L.pack(L.backward_bf16(pp, c16, l16, y))
+    assert g @ g16 / np.linalg.norm(g) / np.linalg.norm(g16) > 0.9999
+    assert abs(float(l1.item()) - L.nll(L.forward(pp, x)[0], y)) < 1e-2

@@ -264,6 +264,15 @@ struct ising_graph {
   std::vector<int32_t> walker_sys;
   DevTables dev{};
   size_t bytes = 0;
+  // With several buckets, bucket b > 0 is launched on side[b - 1] (forked from
+  // and joined back to the caller's stream), so the buckets of one sweep run
+  // side by side and each one's tail overlaps the others.
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[b]: bucket b done
+  ~ising_graph() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipStream_t q : side) (void)hipStreamDestroy(q);
+  }
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -533,6 +542,23 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.cells = (const uint16_t *)(base + L.cells);
   g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
   g->bytes = L.total;
+  if (g->buckets.size() > 1) {
+    for (size_t b = 0; b < g->buckets.size(); ++b) {
+      hipEvent_t ev;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) break;
+      g->ev.push_back(ev);
+      if (b == 0) continue;
+      hipStream_t q;
+      e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);  // default priority
+      if (e != hipSuccess) break;
+      g->side.push_back(q);
+    }
+    if (e != hipSuccess) {
+      delete g;
+      return hip_fail(e, "load_graph: bucket streams");
+    }
+  }
   *out = g;
   return ISING_OK;
 }
@@ -663,7 +689,18 @@ static int32_t enqueue_sweeps(const ising_graph *g, const DevState &d, int64_t *
       seg = (int32_t)std::min<int64_t>(seg, to_swap);
     }
     if (e_series) seg = 1;
-    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
+    if (g->side.empty()) {
+      for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
+    } else {  // fork the buckets onto the side streams, join them back before the swap
+      HIP_TRY(hipEventRecord(g->ev[0], s), "fork");
+      for (size_t b = 1; b < g->buckets.size(); ++b) {
+        HIP_TRY(hipStreamWaitEvent(g->side[b - 1], g->ev[0], 0), "fork wait");
+        HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], seg, 0, g->side[b - 1]), "sweep kernel");
+        HIP_TRY(hipEventRecord(g->ev[b], g->side[b - 1]), "join record");
+      }
+      HIP_TRY(launch_sweep(g->dev, d, g->buckets[0], seg, 0, s), "sweep kernel");
+      for (size_t b = 1; b < g->buckets.size(); ++b) HIP_TRY(hipStreamWaitEvent(s, g->ev[b], 0), "join");
+    }
     *sweeps += seg;
     done += seg;
     int32_t *row = e_series ? e_series + (size_t)(done - 1) * g->slots : nullptr;

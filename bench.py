@@ -90,7 +90,8 @@ def learned_leg(ess_steps, train_rows=1 << 20):
     """Learned cell proposal on the 256 x 32-walker, 4,096-spin workload: train the
     network on the GPU from plain-chain samples, then effective samples per second of
     the plain chain (sweep + swap round per step) against the learned chain (sweep +
-    swap round + one pass of learned cell moves per step), both from the same state."""
+    swap round + one pass of learned cell moves per step) and the heat-bath chain (the
+    same with exact heat-bath cell moves), all from the same state."""
     import numpy as np
     import torch
 
@@ -137,25 +138,36 @@ def learned_leg(ess_steps, train_rows=1 << 20):
     cells_per_pass = sum(s.M * s.L * s.L * s.K for s in wl.systems)
     flops = FLOPS_PER_CELL * cells_per_pass / (launches / passes)
     tflops = flops / (launch_ms / 1e3) / 1e12
+    # heat-bath kernel time, the same way
+    s2 = pa.State(g).copy_from(base)
+    s2.heatbath_cells(19, 0)
+    e0.record(stream)
+    for p in range(passes):
+        s2.heatbath_cells(19, 1 + p)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    hb_ms = e0.elapsed_time(e1) / launches
     chains = {}
-    for name, n in (("plain", None), ("learned", net)):
+    for name, n, hb in (("plain", None, False), ("learned", net, False), ("heatbath", None, True)):
         s2 = pa.State(g).copy_from(base)
-        r = learn.run(s2, ess_steps, n, pass0=1000)
+        r = learn.run(s2, ess_steps, n, pass0=1000, heatbath=hb)
         e = learn.ess_summary(g, r["e"])
         chains[name] = {"ms_per_step": r["ms"] / ess_steps, "ess_coldest": e["coldest_total"],
                         "ess_median_slot": e["median_slot"],
                         "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3),
                         "coldest_mean_energy": float(r["e"][:, 31::32].mean())}
         if "acceptance" in r:
-            chains[name]["cell_acceptance"] = r["acceptance"]
+            chains[name]["cell_acceptance" if n is not None else "cell_changed"] = r["acceptance"]
     return {
         "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": 3000,
         "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems",
         "train": {"rows": int(x.shape[0]), "batch": 4096, "adam_steps": int(len(losses)),
                   "loss_untrained": loss0, "loss_last": float(losses[-1]), "seconds": train_s},
         "acceptance_one_pass": acc,
-        "plain": chains["plain"], "learned": chains["learned"],
+        "plain": chains["plain"], "learned": chains["learned"], "heatbath": chains["heatbath"],
         "ess_per_s_learned_over_plain": chains["learned"]["ess_per_s"] / chains["plain"]["ess_per_s"],
+        "ess_per_s_heatbath_over_plain": chains["heatbath"]["ess_per_s"] / chains["plain"]["ess_per_s"],
+        "heatbath_kernel_ms": hb_ms,
         "roofline": {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
                      "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,

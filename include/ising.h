@@ -278,6 +278,22 @@ int32_t ising_collect_cells(const ising_graph *g, const ising_state *st, int64_t
 int32_t ising_propose_cells(const ising_graph *g, ising_state *st, const ising_mlp *net, uint64_t key,
                             int64_t pass_index, uint64_t *moves, void *stream);
 
+/* One pass of exact heat-bath cell moves (the non-learned control of the
+ * learned proposal), same cells and colour classes: each cell is redrawn from
+ * its conditional Boltzmann law exp(-beta E_c) given the boundary fields
+ * (cost function of Section 1, restricted to the cell).  The cell is
+ * bipartite, so the left half (spins 0..3) is drawn from its marginal over 16
+ * states, log weight beta sum_k b_k s_k + sum_r log(2 cosh(beta h_r)),
+ * h_r = b_r + sum_k J_kr s_k, and then each right spin r is +1 with
+ * probability sigmoid(2 beta h_r).  Uniforms: Philox4x32-10 with key (key mod
+ * 2^32, key div 2^32), counters (cell, walker, pass_index, j), j = 0, 1: word
+ * 0 picks the left state (the first, in index order with bit k = spin k, whose
+ * cumulative weight exceeds u * 2^-32 times the total), words 1..4 the right
+ * spins (+1 iff u * 2^-32 < the probability).  FP32 weights.  moves (device,
+ * nullable) [R][2] += cells visited, cells changed.                          */
+int32_t ising_heatbath_cells(const ising_graph *g, ising_state *st, uint64_t key, int64_t pass_index,
+                             uint64_t *moves, void *stream);
+
 /* ---- host-only helpers (no device work; usable without a GPU) ------------ */
 
 /* thr[d] = ceil(2^32 * exp(-2.0 * beta * d)) - 1 for d = 1..dmax, thr[0] =

@@ -82,6 +82,7 @@ def lib():
             "ising_mlp_adam": ([P, C.c_float, P], i32),
             "ising_collect_cells": ([P, P, i64, i64, i32, P, P, P], i32),
             "ising_propose_cells": ([P, P, P, C.c_uint64, i64, P, P], i32),
+            "ising_heatbath_cells": ([P, P, C.c_uint64, i64, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -269,6 +270,11 @@ class State:
         _check(lib().ising_propose_cells(self.graph.handle, C.byref(self._s), C.byref(net._s), C.c_uint64(key),
                                          int(pass_index), C.c_void_p(moves.data_ptr()) if moves is not None else None,
                                          _stream()))
+
+    def heatbath_cells(self, key, pass_index, moves=None):
+        """One pass of exact heat-bath cell moves (all colour classes)."""
+        _check(lib().ising_heatbath_cells(self.graph.handle, C.byref(self._s), C.c_uint64(key), int(pass_index),
+                                          C.c_void_p(moves.data_ptr()) if moves is not None else None, _stream()))
 
     def swap(self, parity):
         _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))

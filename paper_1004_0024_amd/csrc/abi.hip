@@ -967,6 +967,20 @@ extern "C" int32_t ising_propose_cells(const ising_graph *g, ising_state *st, co
   return ISING_OK;
 }
 
+extern "C" int32_t ising_heatbath_cells(const ising_graph *g, ising_state *st, uint64_t key, int64_t pass_index,
+                                        uint64_t *moves, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "heatbath_cells: NULL graph");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  if (pass_index < 0 || pass_index > (int64_t)UINT32_MAX) return fail(ISING_E_RANGE, "pass_index must fit 32 bits");
+  const DevState d = dev_state(st);
+  for (int32_t p = 0; p < g->max_phases; ++p)
+    HIP_TRY(launch_cell_heatbath(g->dev, d, g->cell_rows, p, key, pass_index, moves, (hipStream_t)stream),
+            "heat-bath cell moves");
+  return ISING_OK;
+}
+
 extern "C" int32_t ising_collect_cells(const ising_graph *g, const ising_state *st, int64_t stride,
                                        int64_t offset, int32_t n, float *x, uint8_t *y, void *stream) {
   if (!g || !x || !y || n < 0 || stride < 1 || offset < 0) return fail(ISING_E_INVAL, "collect_cells: bad arguments");

@@ -1,6 +1,6 @@
-// Cell moves of the learned proposal: boundary fields of the 8-spin cells,
-// training rows from the chain, and the Metropolis-Hastings acceptance of the
-// network's joint proposals.
+// Cell moves: boundary fields of the 8-spin cells, training rows from the
+// chain, the learned proposal with its Metropolis-Hastings test, and the exact
+// heat-bath draw of a cell.
 //
 // A phase is one colour class of cells: cells of one colour share no edge, so
 // all of them (in every walker) are updated at once; the phases run in order.
@@ -112,6 +112,80 @@ __device__ __forceinline__ int cell_energy(uint32_t byte, const int b[8], const 
   return e;
 }
 
+// ---- rows of a colour class ---------------------------------------------------
+// Row = (walker, cell of the class).  A 64-row tile lies in one system (rows
+// of a system start at a multiple of 64), so its record is read once for the
+// wavefront.
+struct CellRow {
+  bool valid;
+  int r, ci;           // global walker, cell index (m*L + y)*L + x
+  int b[8];            // boundary fields
+  int32_t jpack[4];    // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
+  float beta;
+  uint8_t *bytep;      // the cell's byte in the walker's spin words
+  uint32_t cur;        // its current value (bit k = spin k is +1)
+};
+
+__device__ __forceinline__ void load_cell_row(const DevTables &T, const DevState &St, int64_t tile, int lane,
+                                              int32_t phase, CellRow &c) {
+  const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
+  const SysInfo &sy = T.sys[sidx];
+  const int64_t row = tile * 64 + lane;
+  // rows of one system: K x rows < 2^31 (a walker's spins fit in LDS)
+  const uint32_t local = (uint32_t)(row - sy.row0);
+  const uint32_t rows = (uint32_t)sy.rows;
+  const int wk = (int)(local / rows), j = (int)(local - (uint32_t)wk * rows);
+  const int count = phase < sy.n_phases ? sy.pc[phase + 1] - sy.pc[phase] : 0;
+  c.valid = wk < sy.K && j < count;
+  c.r = -1;
+  c.ci = 0;
+  for (int k = 0; k < 8; ++k) c.b[k] = 0;
+  for (int k = 0; k < 4; ++k) c.jpack[k] = 0;
+  c.beta = 0.f;
+  c.bytep = nullptr;
+  c.cur = 0;
+  if (c.valid) {
+    c.r = sy.walker0 + wk;
+    c.ci = T.cells[sy.cl0 + sy.pc[phase] + j];
+    const int LL = sy.grid_L * sy.grid_L;
+    const int m = c.ci / LL, cc = c.ci - m * LL;
+    const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)wk * sy.WW;
+    boundary_fields(T, sy, sp, m, cc, c.b, c.jpack);
+    c.bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)wk * sy.WW + m * sy.RS + ((cc * 8) >> 5)) + (cc & 3);
+    c.cur = *c.bytep;
+    c.beta = (float)T.beta[sy.slot0 + St.temp_of[c.r]];
+  }
+}
+
+// Per-walker sums of a wavefront's rows: energy change, rows, rows counted in
+// `hit`; one atomic each when the lanes share a walker.
+__device__ __forceinline__ void add_cell_moves(const DevState &St, uint64_t *moves, int r, bool valid, bool hit,
+                                               int dE, int lane) {
+  const int r0 = __shfl(r, 0);
+  const bool uniform = __all(r == r0);
+  if (uniform) {
+    if (r0 >= 0) {
+      int tot = dE;
+      for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+      const unsigned long long na = __popcll(__ballot(valid && hit));
+      const unsigned long long nv = __popcll(__ballot(valid));
+      if (lane == 0) {
+        if (tot) atomicAdd(&St.energy[r0], tot);
+        if (moves) {
+          atomicAdd((unsigned long long *)&moves[2 * (size_t)r0], nv);
+          atomicAdd((unsigned long long *)&moves[2 * (size_t)r0 + 1], na);
+        }
+      }
+    }
+  } else if (valid) {
+    if (dE) atomicAdd(&St.energy[r], dE);
+    if (moves) {
+      atomicAdd((unsigned long long *)&moves[2 * (size_t)r], 1ull);
+      if (hit) atomicAdd((unsigned long long *)&moves[2 * (size_t)r + 1], 1ull);
+    }
+  }
+}
+
 // ---- one colour class of cell moves in one launch -----------------------------
 // Each wavefront takes tiles of 64 rows (row = walker x cell of the class, one
 // lane per row): the lane computes its cell's boundary fields and writes the
@@ -200,33 +274,11 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
   for (int64_t tile = (int64_t)blockIdx.x * kProposeWaves + wv; tile < tiles;
        tile += (int64_t)gridDim.x * kProposeWaves) {
     // ---- this lane's row: locate the cell, boundary fields, input ----
-    // a tile lies in one system: its record is read once for the wavefront
-    const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
-    const SysInfo &sy = T.sys[sidx];
-    const int64_t row = tile * 64 + l;
-    // rows of one system: K x rows < 2^31 (a walker's spins fit in LDS)
-    const uint32_t local = (uint32_t)(row - sy.row0);
-    const uint32_t rows = (uint32_t)sy.rows;
-    const int wk = (int)(local / rows), j = (int)(local - (uint32_t)wk * rows);
-    const int count = phase < sy.n_phases ? sy.pc[phase + 1] - sy.pc[phase] : 0;
-    const bool valid = wk < sy.K && j < count;
-    int r = -1, ci = 0;
-    int b[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    float beta = 0.f;
-    uint8_t *bytep = nullptr;
-    uint32_t cur = 0;
-    int32_t jpack[4] = {0, 0, 0, 0};  // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
-    if (valid) {
-      r = sy.walker0 + wk;
-      ci = T.cells[sy.cl0 + sy.pc[phase] + j];
-      const int LL = sy.grid_L * sy.grid_L;
-      const int m = ci / LL, c = ci - m * LL;
-      const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)wk * sy.WW;
-      boundary_fields(T, sy, sp, m, c, b, jpack);
-      bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)wk * sy.WW + m * sy.RS + ((c * 8) >> 5)) + (c & 3);
-      cur = *bytep;
-      beta = (float)T.beta[sy.slot0 + St.temp_of[r]];
-    }
+    CellRow cr;
+    load_cell_row(T, St, tile, l, phase, cr);
+    const bool valid = cr.valid;
+    const int *b = cr.b;
+    const float beta = cr.beta;
     {
       u32x4 *xr = (u32x4 *)(X + l * kS1);
       const u32x4 zero = {0u, 0u, 0u, 0u};
@@ -311,12 +363,13 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((jpack[k] >> (8 * i)) & 0xff)) / 2;
+        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((cr.jpack[k] >> (8 * i)) & 0xff)) / 2;
+      const uint32_t cur = cr.cur;
       const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
       uint32_t wd[12];
 #pragma unroll
       for (int blk = 0; blk < 3; ++blk) {
-        uint32_t c4[4] = {(uint32_t)ci, (uint32_t)r, (uint32_t)pass_index, (uint32_t)blk};
+        uint32_t c4[4] = {(uint32_t)cr.ci, (uint32_t)cr.r, (uint32_t)pass_index, (uint32_t)blk};
         philox4x32(c4, k0, k1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) wd[4 * blk + q] = c4[q];
@@ -336,35 +389,11 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       const float la = -beta * (float)dE + lratio;
       const float ua = (float)wd[8] * 0x1p-32f;
       accept = la >= 0.f || ua < expf(la);
-      if (accept && nb != cur) *bytep = (uint8_t)nb;
+      if (accept && nb != cur) *cr.bytep = (uint8_t)nb;
       if (!accept) dE = 0;
     }
     wave_fence();  // logits read before the next tile's inputs overwrite them
-
-    // per-walker sums: one atomic per wavefront when its lanes share a walker
-    const int r0 = __shfl(r, 0);
-    const bool uniform = __all(r == r0);
-    if (uniform) {
-      if (r0 >= 0) {
-        int tot = dE;
-        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-        const unsigned long long na = __popcll(__ballot(valid && accept));
-        const unsigned long long nv = __popcll(__ballot(valid));
-        if (l == 0) {
-          if (tot) atomicAdd(&St.energy[r0], tot);
-          if (moves) {
-            atomicAdd((unsigned long long *)&moves[2 * (size_t)r0], nv);
-            atomicAdd((unsigned long long *)&moves[2 * (size_t)r0 + 1], na);
-          }
-        }
-      }
-    } else if (valid) {
-      if (dE) atomicAdd(&St.energy[r], dE);
-      if (moves) {
-        atomicAdd((unsigned long long *)&moves[2 * (size_t)r], 1ull);
-        if (accept) atomicAdd((unsigned long long *)&moves[2 * (size_t)r + 1], 1ull);
-      }
-    }
+    add_cell_moves(St, moves, cr.r, valid, accept, dE, l);
   }
 }
 
@@ -376,6 +405,99 @@ hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_
   const int blocks = (int)std::min<int64_t>((tiles + kProposeWaves - 1) / kProposeWaves, 512);
   hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(64 * kProposeWaves), 0, st, t, s, n_sys, rows_total, phase, w, wb, key,
                      pass_index, moves);
+  return hipGetLastError();
+}
+
+// ---- exact heat-bath cell moves (the non-learned control) ----------------------
+// A cell is redrawn from its conditional Boltzmann law given the boundary.  The
+// cell is bipartite, so: the left half (spins 0..3) from its marginal over 16
+// states, log weight beta sum_k b_k s_k + sum_r log(2 cosh(beta h_r)),
+// h_r = b_r + sum_k J_kr s_k; then each right spin r with P(+1) =
+// sigmoid(2 beta h_r).  Words of Philox4x32-10 blocks (cell, walker, pass, 0..1):
+// word 0 picks the left state by its cumulative weight, words 1..4 the right
+// spins.  FP32 with the hardware exp/log.
+__global__ void __launch_bounds__(256) cell_heatbath_kernel(DevTables T, DevState St, int64_t rows_total,
+                                                            int32_t phase, uint64_t key, int64_t pass_index,
+                                                            uint64_t *moves) {
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t tiles = rows_total / 64;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+    CellRow cr;
+    load_cell_row(T, St, tile, l, phase, cr);
+    int dE = 0;
+    bool changed = false;
+    if (cr.valid) {
+      const int *b = cr.b;
+      const float bt = cr.beta;
+      int jin[16];  // J between left spin k and right spin 4 + i at [k*4 + i]
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((cr.jpack[k] >> (8 * i)) & 0xff)) / 2;
+      float lw[16];
+      float mx = -3.0e38f;
+#pragma unroll
+      for (int li = 0; li < 16; ++li) {
+        int sb = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sb += ((li >> k) & 1) ? b[k] : -b[k];
+        float a = bt * (float)sb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int h = b[4 + r];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) h += ((li >> k) & 1) ? jin[k * 4 + r] : -jin[k * 4 + r];
+          const float x = bt * fabsf((float)h);
+          a += x + __logf(1.f + __expf(-2.f * x));  // log(2 cosh x)
+        }
+        lw[li] = a;
+        mx = fmaxf(mx, a);
+      }
+      const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+      uint32_t wd[8];
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        uint32_t c4[4] = {(uint32_t)cr.ci, (uint32_t)cr.r, (uint32_t)pass_index, (uint32_t)blk};
+        philox4x32(c4, k0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wd[4 * blk + q] = c4[q];
+      }
+      float cum[16];
+      float tot = 0.f;
+#pragma unroll
+      for (int li = 0; li < 16; ++li) {
+        tot += __expf(lw[li] - mx);
+        cum[li] = tot;
+      }
+      const float target = (float)wd[0] * 0x1p-32f * tot;
+      int left = 0;  // the first state whose cumulative weight exceeds the target
+#pragma unroll
+      for (int li = 0; li < 16; ++li) left += cum[li] <= target ? 1 : 0;
+      left = left > 15 ? 15 : left;
+      uint32_t nb = (uint32_t)left;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int h = b[4 + r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) h += ((left >> k) & 1) ? jin[k * 4 + r] : -jin[k * 4 + r];
+        const float p = 1.f / (1.f + __expf(-2.f * bt * (float)h));
+        nb |= ((float)wd[1 + r] * 0x1p-32f < p ? 1u : 0u) << (4 + r);
+      }
+      dE = cell_energy(nb, b, jin) - cell_energy(cr.cur, b, jin);
+      changed = nb != cr.cur;
+      if (changed) *cr.bytep = (uint8_t)nb;
+    }
+    add_cell_moves(St, moves, cr.r, cr.valid, changed, dE, l);
+  }
+}
+
+hipError_t launch_cell_heatbath(const DevTables &t, const DevState &s, int64_t rows_total, int32_t phase,
+                                uint64_t key, int64_t pass_index, uint64_t *moves, hipStream_t st) {
+  if (rows_total <= 0) return hipSuccess;
+  const int64_t tiles = rows_total / 64;
+  const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 2048);
+  hipLaunchKernelGGL(cell_heatbath_kernel, dim3(blocks), dim3(256), 0, st, t, s, rows_total, phase, key, pass_index,
+                     moves);
   return hipGetLastError();
 }
 

@@ -119,6 +119,8 @@ hipError_t launch_observables(const DevTables &t, const DevState &s, int32_t R, 
 hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_sys, int64_t rows_total,
                                int32_t phase, const float *w, const uint16_t *wb, uint64_t key, int64_t pass_index,
                                uint64_t *moves, hipStream_t st);
+hipError_t launch_cell_heatbath(const DevTables &t, const DevState &s, int64_t rows_total, int32_t phase,
+                                uint64_t key, int64_t pass_index, uint64_t *moves, hipStream_t st);
 hipError_t launch_collect_cells(const DevTables &t, const DevState &s, int32_t n_sys, int64_t stride,
                                 int64_t offset, int64_t total_cells, int32_t n, float *x, uint8_t *y,
                                 hipStream_t st);

@@ -57,13 +57,16 @@ def train(net, x, y, batch=4096, epochs=2, lr=1e-3):
     return torch.stack([l.reshape(()) for l in losses]).cpu().numpy()
 
 
-def run(state, steps, net=None, key=0, pass0=0, swap_every=1):
-    """`steps` steps of the chain (a sweep, its swap round, and, with a network, one pass
-    of learned cell moves); returns slot energies [steps, slots] (host) and GPU ms."""
+def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False):
+    """`steps` steps of the chain: a sweep and its swap round, then, with a network, one
+    pass of learned cell moves, or with `heatbath`, one pass of exact heat-bath cell
+    moves.  Returns slot energies [steps, slots] (host), GPU ms and the fraction of cells
+    accepted (learned) or changed (heat-bath)."""
     import torch
     g = state.graph
     e = torch.zeros((steps, g.slots), dtype=torch.int32, device=g.tables.device)
-    moves = torch.zeros((g.R, 2), dtype=torch.int64, device=g.tables.device) if net is not None else None
+    cells = net is not None or heatbath
+    moves = torch.zeros((g.R, 2), dtype=torch.int64, device=g.tables.device) if cells else None
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
@@ -71,6 +74,8 @@ def run(state, steps, net=None, key=0, pass0=0, swap_every=1):
         state.sweep(1, swap_every)
         if net is not None:
             state.propose_cells(net, key, pass0 + t, moves)
+        elif heatbath:
+            state.heatbath_cells(key, pass0 + t, moves)
         state.record(e[t])
     t1.record()
     torch.cuda.synchronize()

@@ -147,10 +147,11 @@ def learned_leg(ess_steps, train_rows=1 << 20):
     e1.record(stream)
     torch.cuda.synchronize()
     hb_ms = e0.elapsed_time(e1) / launches
-    chains = {}
+    chains, series = {}, {}
     for name, n, hb in (("plain", None, False), ("learned", net, False), ("heatbath", None, True)):
         s2 = pa.State(g).copy_from(base)
         r = learn.run(s2, ess_steps, n, pass0=1000, heatbath=hb)
+        series[name] = r["e"]
         e = learn.ess_summary(g, r["e"])
         chains[name] = {"ms_per_step": r["ms"] / ess_steps, "ess_coldest": e["coldest_total"],
                         "ess_median_slot": e["median_slot"],
@@ -168,6 +169,10 @@ def learned_leg(ess_steps, train_rows=1 << 20):
         "ess_per_s_learned_over_plain": chains["learned"]["ess_per_s"] / chains["plain"]["ess_per_s"],
         "ess_per_s_heatbath_over_plain": chains["heatbath"]["ess_per_s"] / chains["plain"]["ess_per_s"],
         "heatbath_kernel_ms": hb_ms,
+        # slot mean energies of the cell-move chains against the plain chain, in combined
+        # standard errors (per system and slot)
+        "means_vs_plain": {"learned": learn.compare_means(g, series["learned"], series["plain"]),
+                           "heatbath": learn.compare_means(g, series["heatbath"], series["plain"])},
         "roofline": {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
                      "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,

@@ -99,3 +99,26 @@ def ess_summary(graph, series, burn=0.2):
         allv.extend(e.tolist())
         base += K
     return {"coldest_total": float(np.sum(coldest)), "median_slot": float(np.median(allv))}
+
+
+def compare_means(graph, series_a, series_b, burn=0.2):
+    """Slot mean energies of two chains on the same systems, in units of their combined
+    standard error (variance / ESS per series).  Returns, per slot position in the ladder
+    (0 = hottest), the median |z| over systems, and the fraction of (system, slot) pairs
+    with |z| < 4."""
+    zs = []
+    base = 0
+    for s in graph.systems:
+        K = len(s.beta)
+        za = np.zeros(K)
+        for k in range(K):
+            xa = series_a[:, base + k][int(burn * len(series_a)):].astype(np.float64)
+            xb = series_b[:, base + k][int(burn * len(series_b)):].astype(np.float64)
+            ea, eb = _ess.ess(xa, 0.0), _ess.ess(xb, 0.0)
+            se = np.sqrt(xa.var() / max(ea, 1.0) + xb.var() / max(eb, 1.0))
+            za[k] = (xa.mean() - xb.mean()) / se if se > 0 else 0.0
+        zs.append(za)
+        base += K
+    zs = np.abs(np.array(zs))
+    return {"median_abs_z_by_slot": [float(v) for v in np.median(zs, axis=0)],
+            "frac_abs_z_below_4": float(np.mean(zs < 4.0))}

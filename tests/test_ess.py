@@ -24,3 +24,24 @@ def test_ess_constant_and_short():
     assert ess.tau_int(np.ones(100)) == 0.5
     x = np.random.default_rng(0).normal(size=1000)
     assert 700 < ess.ess(x, burn=0.0) < 1300
+
+
+def test_compare_means_flags_a_shift_only():
+    import numpy as np
+    from paper_1004_0024_amd import learn
+
+    class _S:
+        beta = np.linspace(0.1, 3.0, 4)
+
+    class _G:
+        systems = [_S()] * 50
+
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(4000, 200))
+    b = rng.normal(size=(4000, 200))
+    r = learn.compare_means(_G(), a, b)
+    assert r["frac_abs_z_below_4"] > 0.99
+    assert all(0.4 < z < 1.0 for z in r["median_abs_z_by_slot"])  # |N(0,1)| has median 0.674
+    b[:, 3::4] += 0.5
+    r = learn.compare_means(_G(), a, b)
+    assert r["median_abs_z_by_slot"][3] > 10 and r["frac_abs_z_below_4"] < 0.8

@@ -63,8 +63,26 @@ def lib():
         L.orc_get_swap_mt.argtypes = [P, P, P]
         L.orc_get_counters.argtypes = [P, P, P, P, P]
         L.orc_set_spins.argtypes = [P, i32, P]
+        L.orc_set_acceptance.argtypes = [P, i32]
+        L.orc_exp_approx.argtypes = [C.c_float, i32]
+        L.orc_exp_approx.restype = C.c_float
+        L.orc_approx_threshold.argtypes = [C.c_double, i32, i32]
+        L.orc_approx_threshold.restype = u32
         _lib = L
     return _lib
+
+
+ACCEPT_EXACT, ACCEPT_FAST, ACCEPT_ACCURATE = 0, 1, 2
+
+
+def exp_approx(x, kind):
+    """The paper's approximation of e^x (Sec. 2.4, Fig. 7), FP32, elementwise."""
+    f = lib().orc_exp_approx
+    return np.array([f(float(v), int(kind)) for v in np.ravel(x)], np.float32).reshape(np.shape(x))
+
+
+def approx_threshold(beta, d, kind):
+    return int(lib().orc_approx_threshold(float(beta), int(d), int(kind)))
 
 
 def _ptr(a: np.ndarray):
@@ -168,6 +186,11 @@ class Chain:
     def set_spins(self, w, s):
         s = np.ascontiguousarray(s, np.int8)
         lib().orc_set_spins(self._c, w, _ptr(s))
+
+    def set_acceptance(self, kind):
+        """Flip test: ACCEPT_EXACT (exp), ACCEPT_FAST or ACCEPT_ACCURATE (Sec. 2.4 approximations)."""
+        lib().orc_set_acceptance(self._c, int(kind))
+        return self
 
     @property
     def sweeps_done(self):

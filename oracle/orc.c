@@ -82,6 +82,7 @@ struct orc_chain {
   int32_t *temp_of, *walker_at;
   uint64_t *flips, *sw_att, *sw_acc, near;
   int64_t sweeps, rounds;
+  int32_t accept_kind; /* ORC_ACCEPT_EXACT / _FAST / _ACCURATE */
 };
 
 static void recompute(orc_chain *c, int32_t w) {
@@ -180,6 +181,50 @@ void orc_free(orc_chain *c) {
   free(c);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Approximations of e^x (Sec. 2.4, Fig. 7, Appendix), in FP32 as the paper  */
+/* states them:                                                             */
+/*   fast:     i = round(x * 2^23 log2 e) + 127 * 2^23, read i as a float,  */
+/*             times 2 ln^2 2;  valid for -126 ln 2 <= x < 128 ln 2;        */
+/*   accurate: the same with 2^25 log2 e (so the float is ~ e^{4x}), then   */
+/*             the 4th root; valid for -31.5 ln 2 <= x < 32 ln 2, and 0     */
+/*             below that range.                                            */
+/* "Convert" is rounding to nearest even; the 4th root is two IEEE square   */
+/* roots.  Below the valid range both give 0.                               */
+/* ------------------------------------------------------------------------ */
+float orc_exp_approx(float x, int32_t kind) {
+  const float ln2 = 0.69314718055994531f;
+  const float two_ln2_sq = (float)(2.0 * 0.69314718055994531 * 0.69314718055994531);
+  if (kind == ORC_ACCEPT_FAST) {
+    if (x < -126.0f * ln2) return 0.0f;
+    const float scale = (float)(8388608.0 * 1.4426950408889634); /* 2^23 log2 e */
+    int32_t i = (int32_t)lrintf(x * scale) + 0x3F800000;
+    float f;
+    memcpy(&f, &i, sizeof f);
+    return f * two_ln2_sq;
+  }
+  if (x < -31.5f * ln2) return 0.0f;
+  const float scale = (float)(33554432.0 * 1.4426950408889634); /* 2^25 log2 e */
+  int32_t i = (int32_t)lrintf(x * scale) + 0x3F800000;
+  float f;
+  memcpy(&f, &i, sizeof f);
+  return sqrtf(sqrtf(f * two_ln2_sq));
+}
+
+/* Threshold of the approximate flip test for cost increase 2d (d > 0): with
+ * p = approx(-2 beta d) the test u * 2^-32 < p, u a 32-bit integer, is
+ * u <= ceil(2^32 p) - 1; the threshold is clamped to [0, 2^32 - 1] (so p = 0
+ * leaves u = 0, one draw in 2^32). */
+uint32_t orc_approx_threshold(double beta, int32_t d, int32_t kind) {
+  const float p = orc_exp_approx((float)(-2.0 * beta * (double)d), kind);
+  const double t = ceil((double)p * 4294967296.0) - 1.0;
+  if (t < 0.0) return 0u;
+  if (t > 4294967295.0) return 4294967295u;
+  return (uint32_t)t;
+}
+
+void orc_set_acceptance(orc_chain *c, int32_t kind) { c->accept_kind = kind; }
+
 /* Fig. 1: for each spin in order, draw a uniform; flip if it is below the
  * flip probability; after a flip update the local fields of the neighbours. */
 static void sweep_walker(orc_chain *c, int32_t w) {
@@ -194,10 +239,12 @@ static void sweep_walker(orc_chain *c, int32_t w) {
     int accept;
     if (d <= 0) {
       accept = 1; /* probability min(1, exp(-beta*2d)) = 1 */
-    } else {
+    } else if (c->accept_kind == ORC_ACCEPT_EXACT) {
       double p = exp(-2.0 * beta * (double)d);
       double uniform = (double)u * 0x1p-32; /* in [0, 1) */
       accept = uniform < p;
+    } else {
+      accept = u <= orc_approx_threshold(beta, d, c->accept_kind);
     }
     if (accept) {
       int32_t two_s = 2 * s[i]; /* the old spin value */

@@ -78,6 +78,13 @@ int64_t orc_check_fields(const orc_chain *c);
 /* Overwrite a walker's spins (fields and energy are recomputed). */
 void orc_set_spins(orc_chain *c, int32_t w, const int8_t *s);
 
+/* Flip-test variants: the exact exp, or the paper's approximations of e^x
+ * (Sec. 2.4, Fig. 7).  New chains use the exact one. */
+enum { ORC_ACCEPT_EXACT = 0, ORC_ACCEPT_FAST = 1, ORC_ACCEPT_ACCURATE = 2 };
+void orc_set_acceptance(orc_chain *c, int32_t kind);
+float orc_exp_approx(float x, int32_t kind);
+uint32_t orc_approx_threshold(double beta, int32_t d, int32_t kind);
+
 #ifdef __cplusplus
 }
 #endif

@@ -304,6 +304,24 @@ int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr);
  * index order; *depth = max f + 1.                                           */
 int32_t ising_level_offsets(const ising_system_desc *sys, int32_t *f, int32_t *depth);
 
+/* Flip-test variants.  ISING_ACCEPT_EXACT (the default): thresholds from the
+ * exact exp, as above.  ISING_ACCEPT_FAST / ISING_ACCEPT_ACCURATE: the flip
+ * probability is the paper's approximation of e^x (Section 2.4, Figure 7), in
+ * FP32: x = -2 beta d rounded to FP32, times 2^23 log2 e (fast) or 2^25 log2 e
+ * (accurate), rounded to the nearest integer, plus 0x3F800000, read as a
+ * float, times 2 ln^2 2; the accurate form then takes the 4th root (two IEEE
+ * square roots).  Below the valid range (x < -126 ln 2, resp. -31.5 ln 2) the
+ * probability is 0.  Threshold t = ceil(2^32 p) - 1, clamped to
+ * [0, 2^32 - 1]: u <= t is u * 2^-32 < p, except that p = 0 still passes u = 0
+ * (one draw in 2^32).  These chains sample a slightly different law than the
+ * Boltzmann one; they reproduce the paper's optimised variants.           */
+enum { ISING_ACCEPT_EXACT = 0, ISING_ACCEPT_FAST = 1, ISING_ACCEPT_ACCURATE = 2 };
+/* Host only: the threshold row of one inverse temperature for a variant. */
+int32_t ising_acceptance_row(double beta, int32_t dmax, int32_t kind, uint32_t *thr);
+/* Rewrite every threshold row of the graph for a variant (host -> device copy
+ * on `stream`, then synchronises it); later sweeps use it. */
+int32_t ising_set_acceptance(ising_graph *g, int32_t kind, void *stream);
+
 /* Last error message of this thread ("" if none). */
 const char *ising_last_error(void);
 

@@ -6,6 +6,9 @@ memory and the current stream.  Importing works without a GPU; any call that
 needs the library raises if ``libising.so`` has not been built.
 """
 from .binding import (  # noqa: F401
+    ACCEPT_ACCURATE,
+    ACCEPT_EXACT,
+    ACCEPT_FAST,
     ISING_N_STATS,
     STAT_ATTEMPTS,
     STAT_NEAR,
@@ -16,6 +19,7 @@ from .binding import (  # noqa: F401
     Replay,
     Graph,
     State,
+    acceptance_row,
     lib,
     lib_path,
     level_offsets,

@@ -83,6 +83,8 @@ def lib():
             "ising_collect_cells": ([P, P, i64, i64, i32, P, P, P], i32),
             "ising_propose_cells": ([P, P, P, C.c_uint64, i64, P, P], i32),
             "ising_heatbath_cells": ([P, P, C.c_uint64, i64, P, P], i32),
+            "ising_acceptance_row": ([C.c_double, i32, i32, P], i32),
+            "ising_set_acceptance": ([P, i32, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -120,6 +122,16 @@ def _descs(systems):
 def threshold_row(beta: float, dmax: int) -> np.ndarray:
     out = np.zeros(dmax + 1, np.uint32)
     _check(lib().ising_threshold_row(float(beta), int(dmax), _np_ptr(out)))
+    return out
+
+
+ACCEPT_EXACT, ACCEPT_FAST, ACCEPT_ACCURATE = 0, 1, 2
+
+
+def acceptance_row(beta: float, dmax: int, kind: int) -> np.ndarray:
+    """Threshold row of a flip-test variant (host only)."""
+    out = np.zeros(dmax + 1, np.uint32)
+    _check(lib().ising_acceptance_row(C.c_double(beta), int(dmax), int(kind), _np_ptr(out)))
     return out
 
 
@@ -181,6 +193,10 @@ class Graph:
             _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), 10))
             out.append(dict(zip(self._BUCKET_KEYS, (int(x) for x in v))))
         return out
+
+    def set_acceptance(self, kind):
+        """Flip-test variant for later sweeps: ACCEPT_EXACT, ACCEPT_FAST or ACCEPT_ACCURATE."""
+        _check(lib().ising_set_acceptance(self.handle, int(kind), _stream()))
 
     def set_launch(self, bucket, tpw, walkers_per_group):
         _check(lib().ising_set_launch(self._handle, int(bucket), int(tpw), int(walkers_per_group), _stream()))

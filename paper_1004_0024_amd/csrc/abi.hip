@@ -59,6 +59,37 @@ extern "C" int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr)
   return ISING_OK;
 }
 
+// e^x as Section 2.4 / Figure 7 approximate it, in FP32: scale x by 2^23 log2 e
+// (fast) or 2^25 log2 e (accurate), round to the nearest integer, add the bit
+// pattern of 1.0f, read the result as a float and multiply by 2 ln^2 2; the
+// accurate form then takes the 4th root (two IEEE square roots here).  Below
+// the valid range (-126 ln 2, resp. -31.5 ln 2) the value is 0.
+static float exp_fig7(float x, int32_t kind) {
+  const bool fast = kind == ISING_ACCEPT_FAST;
+  const float lo = (fast ? -126.0f : -31.5f) * 0.69314718055994531f;
+  if (x < lo) return 0.0f;
+  const float mul = (float)((fast ? 8388608.0 : 33554432.0) * 1.4426950408889634);
+  const int32_t bits = (int32_t)lrintf(x * mul) + 0x3F800000;
+  float f;
+  memcpy(&f, &bits, sizeof f);
+  f *= (float)(2.0 * 0.69314718055994531 * 0.69314718055994531);
+  return fast ? f : sqrtf(sqrtf(f));
+}
+
+extern "C" int32_t ising_acceptance_row(double beta, int32_t dmax, int32_t kind, uint32_t *thr) {
+  if (kind == ISING_ACCEPT_EXACT) return ising_threshold_row(beta, dmax, thr);
+  if (kind != ISING_ACCEPT_FAST && kind != ISING_ACCEPT_ACCURATE) return fail(ISING_E_INVAL, "unknown acceptance kind");
+  if (!thr || dmax < 0 || dmax > 1023) return fail(ISING_E_INVAL, "acceptance_row: bad arguments");
+  if (!(beta > 0.0) || !isfinite(beta)) return fail(ISING_E_RANGE, "acceptance_row: beta must be > 0");
+  thr[0] = 0xffffffffu;
+  for (int32_t d = 1; d <= dmax; ++d) {
+    const float p = exp_fig7((float)(-2.0 * beta * (double)d), kind);
+    const double t = ceil(ldexp((double)p, 32)) - 1.0;  // u <= t  <=>  u * 2^-32 < p (p > 0)
+    thr[d] = t < 0.0 ? 0u : (t > 4294967295.0 ? 0xffffffffu : (uint32_t)t);
+  }
+  return ISING_OK;
+}
+
 struct SysHost {
   int32_t S, M, ring, F, deg, dmax, K, cell, FW;
   int32_t grid_L = 0, n_phases = 0;
@@ -262,6 +293,8 @@ struct ising_graph {
   std::vector<Bucket> buckets;
   std::vector<std::vector<int32_t>> bucket_sys;  // systems of each bucket
   std::vector<int32_t> walker_sys;
+  std::vector<double> slot_beta;  // beta of every slot, in slot order
+  int32_t accept_kind = ISING_ACCEPT_EXACT;
   DevTables dev{};
   size_t bytes = 0;
   // With several buckets, bucket b > 0 is launched on side[b - 1] (forked from
@@ -498,6 +531,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
         }
         thr += kThrRow;
         *bt++ = h.beta[k];
+        g->slot_beta.push_back(h.beta[k]);
       }
   }
   {
@@ -564,6 +598,21 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
 }
 
 extern "C" void ising_free_graph(ising_graph *g) { delete g; }
+
+extern "C" int32_t ising_set_acceptance(ising_graph *g, int32_t kind, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "set_acceptance: NULL graph");
+  std::vector<uint32_t> rows((size_t)g->slots * kThrRow);
+  for (size_t k = 0; k < g->slot_beta.size(); ++k) {
+    const int32_t rc = ising_acceptance_row(g->slot_beta[k], kThrRow - 1, kind, rows.data() + k * kThrRow);
+    if (rc) return rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.thr, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+          "set_acceptance copy");
+  HIP_TRY(hipStreamSynchronize(st), "set_acceptance sync");
+  g->accept_kind = kind;
+  return ISING_OK;
+}
 
 extern "C" int32_t ising_n_buckets(const ising_graph *g) { return g ? (int32_t)g->buckets.size() : 0; }
 

@@ -134,3 +134,27 @@ def test_validation_degree():
     assert S_ == 72
     f, depth = pa.level_offsets(make_chimera_system(3, 4, seed=0, K=1))
     assert depth == 6
+
+
+def test_acceptance_rows_match_oracle():
+    """Thresholds of the approximate flip tests (Fig. 7): the library's host code and the
+    oracle's, written separately, agree bit for bit."""
+    import numpy as np
+    import oracle
+    import paper_1004_0024_amd as pa
+    from gen import beta_ladder
+    betas = list(beta_ladder(32, 0.1, 3.0)) + [0.05, 0.731, 1.0, 2.5]
+    for kind in (pa.ACCEPT_FAST, pa.ACCEPT_ACCURATE):
+        for beta in betas:
+            row = pa.acceptance_row(beta, 63, kind)
+            assert row[0] == 0xFFFFFFFF
+            ref = [oracle.approx_threshold(beta, d, kind) for d in range(1, 64)]
+            assert [int(v) for v in row[1:]] == ref, (kind, beta)
+    assert np.array_equal(pa.acceptance_row(0.7, 63, pa.ACCEPT_EXACT), pa.threshold_row(0.7, 63))
+
+
+def test_acceptance_kind_rejected():
+    import pytest
+    import paper_1004_0024_amd as pa
+    with pytest.raises(pa.IsingError):
+        pa.acceptance_row(0.5, 10, 7)

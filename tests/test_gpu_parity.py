@@ -186,3 +186,24 @@ def test_launch_shape_rejected():
             g.set_launch(0, tpw, G)
         assert e.value.code == -2
     assert g.buckets()[0] == before
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_parity_approximate_acceptance(kind):
+    """The paper's approximate flip tests (Fig. 7, fast and accurate): GPU chains with the
+    approximate threshold rows against oracle chains with the same test, bit for bit."""
+    import paper_1004_0024_amd as pa
+    wl = Workload("approx accept", [make_chimera_system(2, 8, 91, 12), make_chimera_system(3, 6, 92, 8)], 0, 1)
+    g, st = make_state(wl)
+    g.set_acceptance(kind)
+    chains = [ch.set_acceptance(kind) for ch in chains_for(wl, [0, 1])]
+    for n in (1, 7, 40):
+        st.sweep(n, 1)
+        for s, ch in enumerate(chains):
+            ch.sweeps(n, 1)
+            compare_system(st, s, ch, f"kind {kind} after {st.sweeps} sweeps")
+    g.set_acceptance(pa.ACCEPT_EXACT)
+    st.sweep(5, 1)
+    for s, ch in enumerate(chains):
+        ch.set_acceptance(0).sweeps(5, 1)
+        compare_system(st, s, ch, "back to the exact test")

@@ -61,3 +61,29 @@ def test_approx_threshold_semantics():
             assert np.array_equal(us <= t, us * 2.0 ** -32 < p)
     # below the valid range p = 0 and only u = 0 passes
     assert oracle.approx_threshold(3.0, 60, oracle.ACCEPT_ACCURATE) == 0
+
+
+def test_approximate_chains_against_enumeration(capsys):
+    """16 spins (one K4,4 cell x 2 open slices), 4 temperatures, swaps every sweep: the exact
+    test matches the Boltzmann means; the approximate tests are measured beside it (their
+    stationary law is not the Boltzmann one; the deviations are printed, not asserted)."""
+    from gen import make_chimera_system
+
+    from . import exact
+    sysm = make_chimera_system(1, 2, seed=8, K=4, ring=False, beta_min=0.3, beta_max=1.5)
+    N, u, v, J, h = sysm.expand()
+    E = exact.energies(N, u, v, J, h)
+    report = {}
+    for kind in (oracle.ACCEPT_EXACT, oracle.ACCEPT_FAST, oracle.ACCEPT_ACCURATE):
+        ch = oracle.Chain.from_system(sysm, 7000 + np.arange(4), 7100).set_acceptance(kind)
+        ch.sweeps(500, 1)
+        rec = ch.sweeps(40000, 1, record_energy=True)["energy"]  # [t, slot]
+        zs = []
+        for k in range(4):
+            m, sd = exact.batch_mean_sigma(rec[:, k].astype(np.float64), 40)
+            zs.append((m - exact.mean_energy(E, float(sysm.beta[k]))) / sd)
+        report[kind] = zs
+    with capsys.disabled():
+        print("\nslot mean energy - Boltzmann mean, in standard errors:",
+              {k: [round(z, 1) for z in v] for k, v in report.items()})
+    assert max(abs(z) for z in report[oracle.ACCEPT_EXACT]) < 5

@@ -83,6 +83,7 @@ def batch_leg(name, n_sweeps, reps=3):
     return {"workload": wl.name, "systems": len(wl.systems), "walkers": g.R,
             "attempts_per_sweep": g.attempts_per_sweep, "sweeps_per_replay": n_sweeps,
             "buckets": len(g.buckets()), "ms_per_sweep": ms / n_sweeps,
+            "launch_shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")} for b in g.buckets()],
             "value": g.attempts_per_sweep * n_sweeps / (ms / 1e3), "unit": "spin-flip attempts/s"}
 
 
@@ -159,8 +160,18 @@ def learned_leg(ess_steps, train_rows=1 << 20):
                         "coldest_mean_energy": float(r["e"][:, 31::32].mean())}
         if "acceptance" in r:
             chains[name]["cell_acceptance" if n is not None else "cell_changed"] = r["acceptance"]
+    # swap cadence (it changes the chain; the objective is effective samples per second)
+    cadence = []
+    for every in (1, 2, 4, 8):
+        s2 = pa.State(g).copy_from(base)
+        r = learn.run(s2, ess_steps // 2, None, swap_every=every)
+        e = learn.ess_summary(g, r["e"])
+        cadence.append({"swap_every": every, "ms_per_step": r["ms"] / (ess_steps // 2),
+                        "ess_coldest": e["coldest_total"], "ess_median_slot": e["median_slot"],
+                        "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3)})
     return {
         "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": 3000,
+        "swap_cadence": cadence,
         "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems",
         "train": {"rows": int(x.shape[0]), "batch": 4096, "adam_steps": int(len(losses)),
                   "loss_untrained": loss0, "loss_last": float(losses[-1]), "seconds": train_s},
@@ -291,7 +302,7 @@ def main():
     }
     del rep, st
     if not args.no_batches:
-        out["other_shapes"] = [batch_leg("C", 20), batch_leg("D", 10)]
+        out["other_shapes"] = [batch_leg("A", 1000), batch_leg("C", 20), batch_leg("D", 10)]
     if not args.no_learned:
         out["effective_samples"] = learned_leg(args.ess_steps)
     if not args.no_cpu_baseline:

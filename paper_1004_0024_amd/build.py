@@ -24,18 +24,24 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every source (one hipcc process each, side by side) and link."""
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    jobs = []
     for src in sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    objs, failed = [], []
+    for src, obj, proc in jobs:
+        out, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(src)
         objs.append(obj)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

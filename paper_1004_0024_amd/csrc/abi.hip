@@ -294,6 +294,11 @@ struct ising_graph {
   std::vector<std::vector<int32_t>> bucket_sys;  // systems of each bucket
   std::vector<int32_t> walker_sys;
   std::vector<double> slot_beta;  // beta of every slot, in slot order
+  bool ladder_all() const {
+    for (const Bucket &b : buckets)
+      if (!b.ladder) return false;
+    return !buckets.empty();
+  }
   int32_t accept_kind = ISING_ACCEPT_EXACT;
   DevTables dev{};
   size_t bytes = 0;
@@ -354,11 +359,18 @@ static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
   if (G < 1) return fail(ISING_E_RANGE, "G must be >= 1");
   G = std::min(G, Kmax);
   if ((int64_t)G * tpw > 1024) return fail(ISING_E_RANGE, "G*tpw exceeds 1024 threads");
-  const size_t lds = (size_t)G * b.walker_words * 4;
+  size_t lds = (size_t)G * b.walker_words * 4;
   if (lds > 160 * 1024) return fail(ISING_E_RANGE, "launch shape needs %zu bytes of LDS (> 160 KiB)", lds);
+  // A workgroup that holds whole systems (G >= Kmax) runs their swap rounds
+  // itself when the swap state fits next to the walkers.
+  const bool ladder =
+      G >= Kmax && Kmax <= 256 && tpw <= 64 && lds + (size_t)kLadderWords * 4 <= 160 * 1024;
+  if (ladder) lds += (size_t)kLadderWords * 4;
   b.tpw = tpw;
   b.cpt = cpt;
   b.G = G;
+  b.kmax = Kmax;
+  b.ladder = ladder ? 1 : 0;
   b.threads = std::max(64, ((G * tpw + 63) / 64) * 64);
   b.lds = lds;
   return ISING_OK;
@@ -366,12 +378,17 @@ static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
 
 // Default shape (measured on MI355X for 8x8 and 4x4 cell templates): at most
 // two columns per thread, up to 256 threads and ~40 KiB of LDS per workgroup.
-static void default_shape(int32_t S, int32_t walker_words, int32_t &tpw, int32_t &G) {
+// Small systems whose whole ladder fits one workgroup take G = Kmax, so their
+// sweeps and swap rounds run in one launch.
+static void default_shape(int32_t S, int32_t walker_words, int32_t Kmax, int32_t &tpw, int32_t &G) {
   int32_t p = 8;
   while (p < S) p <<= 1;
   tpw = p >= 256 ? p / 2 : p;
   G = std::max(1, 256 / tpw);
   while (G > 1 && (size_t)G * walker_words * 4 > 40 * 1024) --G;
+  if (G < Kmax && tpw <= 64 && (int64_t)Kmax * tpw <= 1024 &&
+      ((size_t)Kmax * walker_words + kLadderWords) * 4 <= 160 * 1024)
+    G = Kmax;
 }
 
 static void tile_bucket(ising_graph &g, Bucket &b, const std::vector<int32_t> &systems) {
@@ -451,7 +468,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     }
     b.walker_words = maxw;
     int32_t tpw, G;
-    default_shape(b.S, maxw, tpw, G);
+    default_shape(b.S, maxw, Kmax, tpw, G);
     int32_t rc = shape_bucket(b, tpw, G, Kmax);
     if (rc) return rc;
     tile_bucket(g, b, kv.second);
@@ -727,8 +744,35 @@ extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const
 
 // Enqueue n_sweeps sweeps (and the swap rounds due) starting from the
 // counters *sweeps / *rounds, advancing them.
+// Launch every bucket (bucket b > 0 on side stream b - 1 when there are several,
+// joined back to s).
+static int32_t launch_buckets(const ising_graph *g, const DevState &d, int32_t n, LadderArgs la, hipStream_t s) {
+  if (g->side.empty()) {
+    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, n, 0, s, la), "sweep kernel");
+    return ISING_OK;
+  }
+  HIP_TRY(hipEventRecord(g->ev[0], s), "fork");
+  for (size_t b = 1; b < g->buckets.size(); ++b) {
+    HIP_TRY(hipStreamWaitEvent(g->side[b - 1], g->ev[0], 0), "fork wait");
+    HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], n, 0, g->side[b - 1], la), "sweep kernel");
+    HIP_TRY(hipEventRecord(g->ev[b], g->side[b - 1]), "join record");
+  }
+  HIP_TRY(launch_sweep(g->dev, d, g->buckets[0], n, 0, s, la), "sweep kernel");
+  for (size_t b = 1; b < g->buckets.size(); ++b) HIP_TRY(hipStreamWaitEvent(s, g->ev[b], 0), "join");
+  return ISING_OK;
+}
+
 static int32_t enqueue_sweeps(const ising_graph *g, const DevState &d, int64_t *sweeps, int64_t *rounds,
                               int32_t n_sweeps, int32_t swap_every, int32_t *e_series, hipStream_t s) {
+  if (swap_every > 0 && !e_series && n_sweeps > 0 && g->ladder_all()) {
+    // every system's ladder sits in one workgroup: sweeps and swap rounds in one launch
+    const LadderArgs la{swap_every, 0, *sweeps, *rounds};
+    int32_t rc = launch_buckets(g, d, n_sweeps, la, s);
+    if (rc) return rc;
+    *rounds += (*sweeps + n_sweeps) / swap_every - *sweeps / swap_every;
+    *sweeps += n_sweeps;
+    return ISING_OK;
+  }
   int32_t done = 0;
   while (done < n_sweeps) {
     // Sweeps until the next swap round (or the end, or the next record).
@@ -738,18 +782,8 @@ static int32_t enqueue_sweeps(const ising_graph *g, const DevState &d, int64_t *
       seg = (int32_t)std::min<int64_t>(seg, to_swap);
     }
     if (e_series) seg = 1;
-    if (g->side.empty()) {
-      for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, seg, 0, s), "sweep kernel");
-    } else {  // fork the buckets onto the side streams, join them back before the swap
-      HIP_TRY(hipEventRecord(g->ev[0], s), "fork");
-      for (size_t b = 1; b < g->buckets.size(); ++b) {
-        HIP_TRY(hipStreamWaitEvent(g->side[b - 1], g->ev[0], 0), "fork wait");
-        HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], seg, 0, g->side[b - 1]), "sweep kernel");
-        HIP_TRY(hipEventRecord(g->ev[b], g->side[b - 1]), "join record");
-      }
-      HIP_TRY(launch_sweep(g->dev, d, g->buckets[0], seg, 0, s), "sweep kernel");
-      for (size_t b = 1; b < g->buckets.size(); ++b) HIP_TRY(hipStreamWaitEvent(s, g->ev[b], 0), "join");
-    }
+    int32_t rc = launch_buckets(g, d, seg, LadderArgs{0, 0, 0, 0}, s);
+    if (rc) return rc;
     *sweeps += seg;
     done += seg;
     int32_t *row = e_series ? e_series + (size_t)(done - 1) * g->slots : nullptr;
@@ -871,6 +905,7 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
       for (int32_t G = 1; G <= 32; G <<= 1) {
         Bucket b = orig;
         if (shape_bucket(b, tpw, G, Kmax) != ISING_OK || b.G != G) continue;
+        if (orig.ladder && !b.ladder) continue;  // keep whole ladders in one workgroup
         g->buckets[bi] = b;
         g->tiles.clear();
         for (size_t i = 0; i < g->buckets.size(); ++i) tile_bucket(*g, g->buckets[i], g->bucket_sys[i]);

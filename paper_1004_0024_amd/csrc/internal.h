@@ -61,8 +61,21 @@ struct Bucket {
   int32_t tile0, ntiles;    // tiles [tile0, tile0 + ntiles)
   int32_t threads;          // workgroup size
   int32_t walker_words;     // LDS words per walker slot (max over the bucket's systems)
+  int32_t kmax;             // most walkers of a system in the bucket
+  int32_t ladder;           // 1: every tile holds a whole system (swap rounds can run in the kernel)
   size_t lds;               // dynamic LDS bytes
 };
+
+// In-kernel swap rounds of a ladder bucket: after sweep t of the launch,
+// a round runs when (sweeps0 + t + 1) is a multiple of swap_every (0: none);
+// round n of the launch uses parity (rounds0 + n) mod 2.
+struct LadderArgs {
+  int32_t swap_every, pad;
+  int64_t sweeps0, rounds0;
+};
+// LDS words after the walker slots of a ladder workgroup: the swap stream's
+// 624-word window, walker at each slot, slot of each walker, head and count.
+constexpr int kLadderWords = kMtN + 256 + 256 + 4;
 
 // Generator ring: the 624-word look-back of MT19937 plus one chunk of S words,
 // rounded up to whole chunks.  A kMtN-word copy of its top slots sits in front
@@ -109,7 +122,7 @@ struct DevState {
 // the 624 init_genrand words.
 hipError_t launch_seed(const DevState &s, int32_t R, int32_t n_sys, hipStream_t st);
 hipError_t launch_sweep(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
-                        int32_t init_mode, hipStream_t st);
+                        int32_t init_mode, hipStream_t st, LadderArgs la = LadderArgs{0, 0, 0, 0});
 hipError_t launch_swap(const DevTables &t, const DevState &s, int32_t n_sys, int32_t parity,
                        int32_t *e_row, hipStream_t st);
 hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, int32_t *e_row,

@@ -59,10 +59,43 @@ __device__ __forceinline__ void level_sync() {
   }
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS>
+// One swap round of a system whose walkers all sit in this workgroup (one
+// thread): the same rule and draw order as swap_kernel, on LDS copies of the
+// swap stream (circular 624-word window, head *head), the labels and the
+// walkers' running energies.
+__device__ void ladder_swap_round(const DevTables &T, const DevState &St, const SysInfo &sy, int parity,
+                                  uint32_t *swin, int32_t *wat, int32_t *tof, int32_t *misc,
+                                  const uint32_t *wslots, int PW, int acc_off) {
+#pragma clang fp contract(off)
+  const int K = sy.K, p0 = parity & 1;
+  int h = misc[0];
+  for (int k = p0; k + 1 < K; k += 2) {
+    const int a = wat[k], b = wat[k + 1];
+    const int ea = (int)wslots[a * PW + acc_off], eb = (int)wslots[b * PW + acc_off];
+    const uint32_t x = mt_next_word(swin[h], swin[h + 1 == kMtN ? 0 : h + 1], swin[h + kMtM < kMtN ? h + kMtM : h + kMtM - kMtN]);
+    swin[h] = x;
+    h = h + 1 == kMtN ? 0 : h + 1;
+    const double delta = (T.beta[sy.slot0 + k] - T.beta[sy.slot0 + k + 1]) * (double)(ea - eb);
+    const double xu = (double)mt_temper(x) * 0x1p-32;
+    const double p = exp(delta);
+    const bool accept = (delta >= 0.0) || (xu < p);
+    if (delta < 0.0 && fabs(xu - p) < 1e-12) ++misc[1];
+    St.swap_att[sy.slot0 + k] += 1ull;
+    if (accept) {
+      wat[k] = b;
+      wat[k + 1] = a;
+      tof[a] = k + 1;
+      tof[b] = k;
+      St.swap_acc[sy.slot0 + k] += 1ull;
+    }
+  }
+  misc[0] = h;
+}
+
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER>
 __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, int32_t tile0, int32_t G,
                                                      int32_t TPW, int32_t PW, int32_t n_sweeps,
-                                                     int32_t init_mode) {
+                                                     int32_t init_mode, LadderArgs la) {
   extern __shared__ uint32_t lds[];
   const Tile tile = T.tiles[tile0 + blockIdx.x];
   const SysInfo sy = T.sys[tile.sys];
@@ -107,7 +140,23 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
       wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
     }
   }
-  for (int i = tid; i < nw * 4; i += nthr) wbase(i / 4)[ZP + FW + SWW + kThrRow + (i & 3)] = 0u;
+  // reduction words: running energy (the walker's cost, so a swap round in the
+  // launch can read it), flips, wavefront steps, wavefront steps with a flip
+  for (int i = tid; i < nw * 4; i += nthr)
+    wbase(i / 4)[ZP + FW + SWW + kThrRow + (i & 3)] =
+        ((i & 3) == 0 && !init_mode) ? (uint32_t)St.energy[sy.walker0 + tile.w0 + i / 4] : 0u;
+  // ladder tiles (the whole system in this workgroup): swap state in LDS
+  const bool ladder = LADDER && la.swap_every > 0 && !init_mode;
+  uint32_t *swin = lds + G * PW;
+  int32_t *wat = (int32_t *)(swin + kMtN), *tof = wat + 256, *misc = tof + 256;
+  if (ladder) {
+    for (int j = tid; j < kMtN; j += nthr) swin[j] = St.swap_mt[(size_t)tile.sys * kMtN + j];
+    for (int k = tid; k < nw; k += nthr) {
+      wat[k] = St.walker_at[sy.slot0 + k];
+      tof[k] = St.temp_of[sy.walker0 + k];
+    }
+    if (tid == 0) misc[0] = misc[1] = 0;
+  }
 
   // ---- this thread's walker and columns ----
   const int gw = tid / TPW, t = tid - gw * TPW;
@@ -209,6 +258,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 
   int gslot = c0 * S;  // generator slot of the next chunk
   int dE = 0, nfl = 0;  // per lane: sum of d over flips (the cost changes by 2d), flips
+  int64_t n_rounds = 0;  // swap rounds run in this launch (ladder tiles)
   uint32_t st_steps = 0, st_flip = 0, nfl_w = 0;  // per wavefront
 
   gen_chunk(gslot, 0);
@@ -295,6 +345,23 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         }
         level_sync<WS>();
       }
+      if (ladder && (la.sweeps0 + sw + 1) % la.swap_every == 0) {
+        // running energies up to date, one thread swaps, then every walker
+        // takes the threshold row of its (new) slot
+        if (live && dE) atomicAdd(&acc[0], 2 * dE);
+        dE = 0;
+        __syncthreads();
+        if (tid == 0)
+          ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
+                            ZP + FW + SWW + kThrRow);
+        ++n_rounds;
+        __syncthreads();
+        for (int i = tid; i < nw * kThrRow; i += nthr) {
+          const int w = i / kThrRow, j = i - w * kThrRow;
+          wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + tof[w]) * kThrRow + j];
+        }
+        __syncthreads();
+      }
     }
   }
 
@@ -324,17 +391,26 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   if (!init_mode && tid < nw) {
     const int r = sy.walker0 + tile.w0 + tid;
     const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + SWW + kThrRow);
-    St.energy[r] += a[0];
+    St.energy[r] = a[0];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
     St.wsteps[2 * (size_t)r] += (unsigned long long)(uint32_t)a[2];
     St.wsteps[2 * (size_t)r + 1] += (unsigned long long)(uint32_t)a[3];
   }
+  if (ladder) {
+    const int h = misc[0];
+    for (int j = tid; j < kMtN; j += nthr) St.swap_mt[(size_t)tile.sys * kMtN + j] = swin[(h + j) % kMtN];
+    for (int k = tid; k < nw; k += nthr) {
+      St.walker_at[sy.slot0 + k] = wat[k];
+      St.temp_of[sy.walker0 + k] = tof[k];
+    }
+    if (tid == 0 && misc[1]) atomicAdd((unsigned long long *)&St.stats[0], (unsigned long long)misc[1]);
+  }
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS>
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER = false>
 static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bucket &b,
-                                 int32_t n_sweeps, int32_t init_mode, hipStream_t st) {
-  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS>;
+                                 int32_t n_sweeps, int32_t init_mode, hipStream_t st, LadderArgs la) {
+  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER>;
   // Allow the whole LDS once per instantiation (outside any stream capture
   // after the first launch of a variant).
   static bool lds_limit_set = false;
@@ -345,48 +421,58 @@ static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bu
     lds_limit_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(b.ntiles), dim3(b.threads), b.lds, st, t, s, b.tile0, b.G, b.tpw,
-                     b.walker_words, n_sweeps, init_mode);
+                     b.walker_words, n_sweeps, init_mode, la);
   return hipGetLastError();
 }
 
 template <int NX, bool CELL, bool RING>
 static hipError_t launch_cpt(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
-                             int32_t init_mode, hipStream_t st) {
+                             int32_t init_mode, hipStream_t st, LadderArgs la) {
   const bool ws = b.tpw <= 64;
+  if (b.ladder) {  // whole ladders in one workgroup: walkers of at most one wavefront each
+    if (!ws) return hipErrorInvalidValue;
+    switch (b.cpt) {
+      case 1: return launch_variant<NX, CELL, RING, 1, true, true>(t, s, b, n_sweeps, init_mode, st, la);
+      case 2: return launch_variant<NX, CELL, RING, 2, true, true>(t, s, b, n_sweeps, init_mode, st, la);
+      case 4: return launch_variant<NX, CELL, RING, 4, true, true>(t, s, b, n_sweeps, init_mode, st, la);
+      case 8: return launch_variant<NX, CELL, RING, 8, true, true>(t, s, b, n_sweeps, init_mode, st, la);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (b.cpt) {
-    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true>(t, s, b, n_sweeps, init_mode, st)
-                      : launch_variant<NX, CELL, RING, 1, false>(t, s, b, n_sweeps, init_mode, st);
-    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true>(t, s, b, n_sweeps, init_mode, st)
-                      : launch_variant<NX, CELL, RING, 2, false>(t, s, b, n_sweeps, init_mode, st);
-    case 4: return ws ? launch_variant<NX, CELL, RING, 4, true>(t, s, b, n_sweeps, init_mode, st)
-                      : launch_variant<NX, CELL, RING, 4, false>(t, s, b, n_sweeps, init_mode, st);
-    case 8: return ws ? launch_variant<NX, CELL, RING, 8, true>(t, s, b, n_sweeps, init_mode, st)
-                      : launch_variant<NX, CELL, RING, 8, false>(t, s, b, n_sweeps, init_mode, st);
+    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 1, false>(t, s, b, n_sweeps, init_mode, st, la);
+    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 2, false>(t, s, b, n_sweeps, init_mode, st, la);
+    case 4: return ws ? launch_variant<NX, CELL, RING, 4, true>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 4, false>(t, s, b, n_sweeps, init_mode, st, la);
+    case 8: return ws ? launch_variant<NX, CELL, RING, 8, true>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 8, false>(t, s, b, n_sweeps, init_mode, st, la);
   }
   return hipErrorInvalidValue;
 }
 
 template <bool CELL, bool RING>
 static hipError_t launch_nx(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
-                            int32_t init_mode, hipStream_t st) {
+                            int32_t init_mode, hipStream_t st, LadderArgs la) {
   switch (b.nx) {
-    case 0: return launch_cpt<0, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 2: return launch_cpt<2, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 4: return launch_cpt<4, CELL, RING>(t, s, b, n_sweeps, init_mode, st);
-    case 6: if (!CELL) return launch_cpt<6, CELL, RING>(t, s, b, n_sweeps, init_mode, st); break;
-    case 8: if (!CELL) return launch_cpt<8, CELL, RING>(t, s, b, n_sweeps, init_mode, st); break;
+    case 0: return launch_cpt<0, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
+    case 2: return launch_cpt<2, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
+    case 4: return launch_cpt<4, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
+    case 6: if (!CELL) return launch_cpt<6, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la); break;
+    case 8: if (!CELL) return launch_cpt<8, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la); break;
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
-                        int32_t init_mode, hipStream_t st) {
+                        int32_t init_mode, hipStream_t st, LadderArgs la) {
   if (b.ntiles == 0) return hipSuccess;
   if (b.cell)
-    return b.ring ? launch_nx<true, true>(t, s, b, n_sweeps, init_mode, st)
-                  : launch_nx<true, false>(t, s, b, n_sweeps, init_mode, st);
-  return b.ring ? launch_nx<false, true>(t, s, b, n_sweeps, init_mode, st)
-                : launch_nx<false, false>(t, s, b, n_sweeps, init_mode, st);
+    return b.ring ? launch_nx<true, true>(t, s, b, n_sweeps, init_mode, st, la)
+                  : launch_nx<true, false>(t, s, b, n_sweeps, init_mode, st, la);
+  return b.ring ? launch_nx<false, true>(t, s, b, n_sweeps, init_mode, st, la)
+                : launch_nx<false, false>(t, s, b, n_sweeps, init_mode, st, la);
 }
 
 }  // namespace ising

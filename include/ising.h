@@ -121,7 +121,11 @@ int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row
  * workgroup holds `walkers_per_group` walkers.  Shapes change speed only: the
  * chain is the same for every shape.  bucket_info writes, in this order:
  *   S, systems, walkers, attempts per sweep, tpw, walkers per group, columns
- *   per thread, workgroup threads, LDS bytes per workgroup, workgroups.
+ *   per thread, workgroup threads, LDS bytes per workgroup, workgroups, ladder
+ *   (1 when every workgroup holds whole systems, at most 64 threads per walker,
+ *   and the swap state fits: then, when every bucket is a ladder bucket,
+ *   ising_sweep runs the swap rounds inside the sweep kernel, one launch per
+ *   call; the chain is the same).
  * set_launch returns ISING_E_RANGE for a shape that does not fit (threads,
  * LDS, columns per thread) and leaves the bucket unchanged.                  */
 int32_t ising_n_buckets(const ising_graph *g);

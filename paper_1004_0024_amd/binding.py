@@ -184,13 +184,13 @@ class Graph:
     def handle(self):
         return self._handle
 
-    _BUCKET_KEYS = ["S", "systems", "walkers", "attempts", "tpw", "G", "cpt", "threads", "lds", "tiles"]
+    _BUCKET_KEYS = ["S", "systems", "walkers", "attempts", "tpw", "G", "cpt", "threads", "lds", "tiles", "ladder"]
 
     def buckets(self):
         out = []
         for b in range(lib().ising_n_buckets(self._handle)):
-            v = np.zeros(10, np.int64)
-            _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), 10))
+            v = np.zeros(11, np.int64)
+            _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), 11))
             out.append(dict(zip(self._BUCKET_KEYS, (int(x) for x in v))))
         return out
 

@@ -642,9 +642,9 @@ extern "C" int32_t ising_bucket_info(const ising_graph *g, int32_t bucket, int64
     walkers += g->sys[s].K;
     attempts += (int64_t)g->sys[s].K * g->sys[s].S * g->sys[s].M;
   }
-  const int64_t v[10] = {b.S, (int64_t)g->bucket_sys[bucket].size(), walkers, attempts, b.tpw, b.G,
-                         b.cpt, b.threads, (int64_t)b.lds, b.ntiles};
-  for (int32_t i = 0; i < n && i < 10; ++i) out[i] = v[i];
+  const int64_t v[11] = {b.S, (int64_t)g->bucket_sys[bucket].size(), walkers, attempts, b.tpw, b.G,
+                         b.cpt, b.threads, (int64_t)b.lds, b.ntiles, b.ladder};
+  for (int32_t i = 0; i < n && i < 11; ++i) out[i] = v[i];
   return ISING_OK;
 }
 

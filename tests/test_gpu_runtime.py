@@ -113,3 +113,30 @@ def test_record_slots_matches_observables():
     want[base[sys_of] + obs[:, 3]] = obs[:, 2]  # obs[:, 3] is the slot within the system
     assert np.array_equal(got, want)
     assert np.array_equal(obs[:, 0], obs[:, 2])
+
+
+@pytest.mark.parametrize("ladder", [True, False])
+def test_in_kernel_swap_rounds_match_oracle(ladder):
+    """Whole ladders in one workgroup (swap rounds inside the sweep kernel, one launch per
+    call) and the same systems split over workgroups (swap kernel between sweeps): both
+    chains equal the oracle's, with swap cadences 1 and 3 and a graph replay."""
+    wl = Workload("ladder", [make_chimera_system(2, 5, 51, 12), make_chimera_system(2, 4, 52, 9)], 0, 1)
+    g, st = make_state(wl)
+    if not ladder:
+        g.set_launch(0, 32, 4)
+    say("buckets", g.buckets())
+    assert all(b["ladder"] == (1 if ladder else 0) for b in g.buckets())
+    chains = chains_for(wl, [0, 1])
+    for n, every in ((1, 1), (7, 1), (5, 3), (4, 3)):
+        st.sweep(n, every)
+        for s, ch in enumerate(chains):
+            ch.sweeps(n, every)
+            compare_system(st, s, ch, f"ladder={ladder} {n} sweeps, swap every {every}")
+    # a captured loop of 6 sweeps with swaps every 3, replayed twice
+    rep = st.capture(6, swap_every=3)
+    for _ in range(2):
+        rep.launch()
+        rep.stream.synchronize()
+        for s, ch in enumerate(chains):
+            ch.sweeps(6, 3)
+            compare_system(st, s, ch, f"ladder={ladder} replay")

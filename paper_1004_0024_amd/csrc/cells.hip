@@ -32,14 +32,12 @@ __device__ __forceinline__ void philox4x32(uint32_t c[4], uint32_t k0, uint32_t 
   }
 }
 
-// Last system whose first index (row0 or cell0) is <= v.
-template <bool ROWS>
+// Last system whose first cell (walker-major numbering) is <= v.
 __device__ __forceinline__ int find_system(const SysInfo *sys, int n_sys, int64_t v) {
   int lo = 0, hi = n_sys;  // invariant: answer in [lo, hi)
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    const int64_t first = ROWS ? sys[mid].row0 : sys[mid].cell0;
-    if (first <= v) lo = mid;
+    if (sys[mid].cell0 <= v) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -507,7 +505,7 @@ __global__ void collect_cells_kernel(DevTables T, DevState St, int32_t n_sys, in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t g = (offset + (int64_t)i * stride) % total_cells;
-  const SysInfo sy = T.sys[find_system<false>(T.sys, n_sys, g)];
+  const SysInfo sy = T.sys[find_system(T.sys, n_sys, g)];
   const int LL = sy.grid_L * sy.grid_L;
   const int64_t per_walker = (int64_t)sy.M * LL;
   const int64_t local = g - sy.cell0;

@@ -97,6 +97,7 @@ struct SysHost {
   int32_t pc[5] = {0, 0, 0, 0, 0};
   std::vector<TmplSpin> tmpl;
   std::vector<uint32_t> fifo;  // (queue base << 8) | log2(depth) per template spin
+  std::vector<uint32_t> cellrec;  // grid templates: kCellRecWords words per template cell
   std::vector<double> beta;
 };
 
@@ -264,6 +265,25 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
         out.cells.insert(out.cells.end(), ph[p].begin(), ph[p].end());
       }
       for (int32_t p = out.n_phases; p < 5; ++p) out.pc[p] = (int32_t)out.cells.size();
+      // cell records: the neighbours outside the cell, by direction and bit
+      out.cellrec.assign((size_t)L * L * kCellRecWords, 0u);
+      for (int32_t c = 0; c < L * L; ++c) {
+        uint32_t *rec = out.cellrec.data() + (size_t)c * kCellRecWords;
+        for (int32_t k = 0; k < 8; ++k) {
+          const TmplSpin &t = out.tmpl[c * 8 + k];
+          int32_t e = 0;
+          for (int32_t j = 4; j < t.deg; ++j) {
+            const int32_t nb = t.nbr[j], cn = nb >> 3;
+            const int32_t dir = cn == c - L ? 0 : cn == c + L ? 1 : cn == c - 1 ? 2 : 3;
+            const uint32_t ent = (uint32_t)(uint8_t)t.J[j] | ((uint32_t)(8 * dir + (nb & 7)) << 8);
+            rec[2 * k + (e >> 1)] |= ent << (16 * (e & 1));
+            ++e;
+          }
+          rec[16 + (k >> 2)] |= (uint32_t)(uint8_t)t.h << (8 * (k & 3));
+          rec[18 + (k >> 2)] |= (uint32_t)(uint8_t)t.Jtau << (8 * (k & 3));
+          if (k < 4) rec[20 + k] = (uint32_t)t.jpack;
+        }
+      }
     }
   }
   out.beta.assign(d.beta, d.beta + d.n_temps);
@@ -316,13 +336,13 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, total;
+  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, cellrec, total;
 };
 
 // Device tables.  Room for one tile per walker, so any launch shape can be
 // installed later without reallocating.
 static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R, int64_t n_cells,
-                         int64_t cell_rows) {
+                         int64_t cell_rows, int64_t n_cellrec) {
   Layout L{};
   size_t o = 0;
   n_tiles = std::max(n_tiles, R);
@@ -344,6 +364,8 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   o = align256(o + sizeof(uint16_t) * std::max<int64_t>(n_cells, 1));
   L.rtiles = o;
   o = align256(o + sizeof(int32_t) * std::max<int64_t>(cell_rows / 64, 1));
+  L.cellrec = o;
+  o = align256(o + sizeof(uint32_t) * std::max<int64_t>(n_cellrec, 1));
   L.total = o;
   return L;
 }
@@ -402,7 +424,7 @@ static void tile_bucket(ising_graph &g, Bucket &b, const std::vector<int32_t> &s
 static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
   g.n_sys = (int32_t)hs.size();
   g.sys.resize(hs.size());
-  int64_t walker = 0, slot = 0, word = 0, tmpl = 0, cl = 0;
+  int64_t walker = 0, slot = 0, word = 0, tmpl = 0, cl = 0, cb = 0;
   for (size_t s = 0; s < hs.size(); ++s) {
     const SysHost &h = hs[s];
     SysInfo &si = g.sys[s];
@@ -423,6 +445,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.cell = h.cell;
     si.nx = h.deg - (h.cell ? 4 : 0);
     si.fifo_words = h.FW;
+    si.cb0 = (int32_t)cb;
     si.grid_L = h.grid_L;
     si.n_phases = h.n_phases;
     si.cl0 = (int32_t)cl;
@@ -435,6 +458,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     g.total_cells += h.grid_L ? (int64_t)h.grid_L * h.grid_L * h.M * h.K : 0;
     g.max_phases = std::max(g.max_phases, h.n_phases);
     cl += (int64_t)h.cells.size();
+    cb += (int64_t)h.cellrec.size() / kCellRecWords;
     walker += h.K;
     slot += h.K;
     word += (int64_t)si.WW * h.K;
@@ -496,12 +520,13 @@ extern "C" int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys
   ising_graph g;
   rc = plan(hs, g);
   if (rc) return rc;
-  int64_t ntm = 0, ncl = 0;
+  int64_t ntm = 0, ncl = 0, ncr = 0;
   for (auto &h : hs) {
     ntm += h.S;
     ncl += (int64_t)h.cells.size();
+    ncr += (int64_t)h.cellrec.size();
   }
-  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl, g.cell_rows).total;
+  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl, g.cell_rows, ncr).total;
   return ISING_OK;
 }
 
@@ -519,12 +544,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
     delete g;
     return rc;
   }
-  int64_t ntm = 0, ncl = 0;
+  int64_t ntm = 0, ncl = 0, ncr = 0;
   for (auto &h : hs) {
     ntm += h.S;
     ncl += (int64_t)h.cells.size();
+    ncr += (int64_t)h.cellrec.size();
   }
-  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl, g->cell_rows);
+  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl, g->cell_rows, ncr);
   if (bytes < L.total) {
     delete g;
     return fail(ISING_E_SIZE, "dev_tables has %zu bytes, needs %zu", bytes, L.total);
@@ -565,6 +591,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
       co += h.cells.size();
     }
   }
+  {
+    uint32_t *cr = (uint32_t *)(host.data() + L.cellrec);
+    for (auto &h : hs) {
+      memcpy(cr, h.cellrec.data(), sizeof(uint32_t) * h.cellrec.size());
+      cr += h.cellrec.size();
+    }
+  }
   {  // system of each 64-row tile of cell moves: the last system whose rows start at or before it
     int32_t *ts = (int32_t *)(host.data() + L.rtiles);
     int32_t sidx = 0;
@@ -592,6 +625,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.fifo = (const uint32_t *)(base + L.fifo);
   g->dev.cells = (const uint16_t *)(base + L.cells);
   g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
+  g->dev.cellrec = (const uint32_t *)(base + L.cellrec);
   g->bytes = L.total;
   if (g->buckets.size() > 1) {
     for (size_t b = 0; b < g->buckets.size(); ++b) {

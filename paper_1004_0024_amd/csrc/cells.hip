@@ -46,11 +46,10 @@ __device__ __forceinline__ int find_system(const SysInfo *sys, int n_sys, int64_
 // Boundary fields b_k = h_k + sum_{j outside the cell} J_kj s_j of cell c of slice m.
 // In-slice edges between cells join grid neighbours only (checked when the
 // graph is loaded), so every outside neighbour in the slice lies in cell c - L,
-// c + L, c - 1 or c + 1: the four spin words holding those cells, and the
-// words of cell c in the slices before and after, are read once up front and
-// each neighbour's bit is picked from them.  A template record is read as two
-// 16-byte words (neighbours; couplings, h, J_tau, level, degree, packed
-// in-cell couplings) and unpacked in registers.
+// c + L, c - 1 or c + 1.  Their four bytes are packed into one word, and the
+// cell record gives, for every outside neighbour, its coupling and its bit in
+// that word; the tau neighbours are spin k of the cell in the slices before
+// and after.
 __device__ __forceinline__ void boundary_fields(const DevTables &T, const SysInfo &sy, const uint32_t *sp, int m,
                                                 int c, int b[8], int32_t jpack[4] = nullptr) {
   const int M = sy.M, L = sy.grid_L;
@@ -60,31 +59,35 @@ __device__ __forceinline__ void boundary_fields(const DevTables &T, const SysInf
   const uint32_t *row = sp + m * sy.RS;
   const int cu = y > 0 ? c - L : c, cd = y < L - 1 ? c + L : c;
   const int cl = x > 0 ? c - 1 : c, cr = x < L - 1 ? c + 1 : c;
-  const uint32_t wu = row[cu >> 2], wd = row[cd >> 2], wl = row[cl >> 2], wr = row[cr >> 2];
-  const uint32_t own_shift = (c & 3) * 8;
-  const uint32_t bp = has_p ? (sp[mp * sy.RS + (c >> 2)] >> own_shift) & 0xffu : 0u;
-  const uint32_t bn = has_n ? (sp[mn * sy.RS + (c >> 2)] >> own_shift) & 0xffu : 0u;
-  const uint4 *rec = (const uint4 *)(T.tmpl + sy.tmpl0 + c * 8);
+  auto cell_byte = [](uint32_t w, int cc) { return (w >> ((cc & 3) * 8)) & 0xffu; };
+  const uint32_t nbytes = cell_byte(row[cu >> 2], cu) | (cell_byte(row[cd >> 2], cd) << 8) |
+                          (cell_byte(row[cl >> 2], cl) << 16) | (cell_byte(row[cr >> 2], cr) << 24);
+  const uint32_t bp = has_p ? cell_byte(sp[mp * sy.RS + (c >> 2)], c) : 0u;
+  const uint32_t bn = has_n ? cell_byte(sp[mn * sy.RS + (c >> 2)], c) : 0u;
+  const uint4 *rec = (const uint4 *)(T.cellrec + (size_t)(sy.cb0 + c) * kCellRecWords);
+  const uint4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3], hq = rec[4], jq = rec[5];
+  const uint32_t ent[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                            r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const uint4 lo = rec[2 * k], hi = rec[2 * k + 1];  // lo: nbr[0..7]; hi: J[0..7], h, Jtau, f, deg, jpack
-    const int deg = (int)(hi.z >> 24);
-    const int jtau = (int)(int8_t)((hi.z >> 8) & 0xffu);
-    int f = (int)(int8_t)(hi.z & 0xffu);
+    int f = (int)(int8_t)((((k < 4) ? hq.x : hq.y) >> (8 * (k & 3))) & 0xffu);
+    const int jtau = (int)(int8_t)((((k < 4) ? hq.z : hq.w) >> (8 * (k & 3))) & 0xffu);
 #pragma unroll
-    for (int j = 4; j < kMaxDeg; ++j) {  // the first 4 neighbours are the in-cell partners
-      if (j < deg) {
-        const int nb = (int)(int16_t)((((j < 6) ? lo.z : lo.w) >> (16 * (j & 1))) & 0xffffu);
-        const int Jv = (int)(int8_t)((hi.y >> (8 * (j - 4))) & 0xffu);
-        const int cn = nb >> 3;
-        const uint32_t w = cn == cu ? wu : cn == cd ? wd : cn == cl ? wl : wr;
-        f += Jv * (2 * (int)((w >> (nb & 31)) & 1u) - 1);
-      }
+    for (int e = 0; e < 4; ++e) {  // an unused entry has J = 0
+      const uint32_t v = ent[2 * k + (e >> 1)] >> (16 * (e & 1));
+      const int J = (int)(int8_t)(v & 0xffu);
+      const int bit = (int)((nbytes >> ((v >> 8) & 31u)) & 1u);
+      f += J * (2 * bit - 1);
     }
     if (has_p) f += jtau * (2 * (int)((bp >> k) & 1u) - 1);
     if (has_n) f += jtau * (2 * (int)((bn >> k) & 1u) - 1);
     b[k] = f;
-    if (jpack && k < 4) jpack[k] = (int32_t)hi.w;
+  }
+  if (jpack) {
+    jpack[0] = (int32_t)jq.x;
+    jpack[1] = (int32_t)jq.y;
+    jpack[2] = (int32_t)jq.z;
+    jpack[3] = (int32_t)jq.w;
   }
 }
 

@@ -23,8 +23,8 @@ struct SysInfo {
   int32_t deg;             // max in-slice degree of the template
   int32_t cell;            // 1: every spin's first 4 neighbours are the other half of its 8-spin cell
   int32_t nx;              // neighbours handled one by one (deg, or deg - 4 for cell templates)
-  int32_t fifo_words;      // per walker: sum over template spins of their uniform-queue depths
-  int32_t pad;
+  int32_t fifo_words;      // per walker: LDS words of the uniform queues
+  int32_t cb0;             // first cell record (kCellRecWords words each) of the template's cells
   // cell moves (learned proposal); grid_L = 0 when the template is not a grid of 8-spin cells
   int32_t grid_L;          // cells per grid side: cell (m, y, x) = spins m*S + (y*L + x)*8 + 0..7
   int32_t n_phases;        // colour classes of cells (2, or 4 on a ring of odd length)
@@ -48,6 +48,16 @@ struct TmplSpin {
   int32_t jpack;
 };
 static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
+
+// Cell record of a template cell c (cell moves), kCellRecWords uint32 words:
+//   [2k], [2k+1]  spin k's in-slice neighbours outside the cell, four 16-bit
+//                 entries: low byte J (int8, 0 for an unused entry), bits 8..12
+//                 the bit of that neighbour in the word (cell byte above) | (below
+//                 << 8) | (left << 16) | (right << 24);
+//   [16], [17]    h_k as int8, k = 0..3 and 4..7;
+//   [18], [19]    J_tau of spin k as int8;
+//   [20 + k]      2J of spin k (< 4) to the spins 4 + i of the cell, byte i.
+constexpr int kCellRecWords = 24;
 
 // One workgroup of the sweep: `nw` walkers of system `sys` starting at `w0`.
 struct Tile {
@@ -108,6 +118,7 @@ struct DevTables {
   const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
   const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
   const int32_t *tile_sys;    // per 64-row tile of cell moves: its system
+  const uint32_t *cellrec;    // cell records of the grid templates (see kCellRecWords)
 };
 
 struct DevState {

@@ -4,7 +4,9 @@
 A step is one full run of the throughput workload: every walker of 256
 systems (8x8 K4,4 cells x 64 Trotter slices = 32,768 spins, 32 walkers each)
 does 100 sequential-order sweeps with a swap round after every sweep.  Inputs
-and state are resident in HBM before the timed region.  Prints one JSON line.
+and state are resident in HBM before the timed region; 10 timed steps by
+default (median and spread of the step times are reported).  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -194,7 +196,7 @@ def learned_leg(ess_steps, train_rows=1 << 20):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="B")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -259,6 +261,9 @@ def main():
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     sweep_ms = [evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for k in range(args.steps) for t in range(n_sw)]
+    # per-step times: from the first sweep's start event of a step to the next step's
+    step_ms = [evs[k][0].elapsed_time(evs[k + 1][0]) for k in range(args.steps - 1)] + \
+        [evs[args.steps - 1][0].elapsed_time(stop)]
     # The same step as one captured HIP graph (sweep + swap kernels, no host work).
     rep = st.capture(n_sw, swap_every=1)
     rep.launch()
@@ -282,6 +287,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "step_ms": {"median": sorted(step_ms)[len(step_ms) // 2], "min": min(step_ms), "max": max(step_ms)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

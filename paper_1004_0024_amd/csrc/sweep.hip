@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
   } else {
     const int levels = M + F - 1;
-    const bool wave_walker = TPW >= 64;  // a wavefront's lanes belong to one walker
+    const bool wave_walker = !WS || TPW >= 64;  // a wavefront's lanes belong to one walker
     for (int sw = 0; sw < n_sweeps; ++sw) {
       const int chunk0 = sw * M;
       for (int lv = 0; lv < levels; ++lv) {
@@ -293,7 +293,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
           const bool active = (unsigned)m < (unsigned)M;
           // Wavefronts with no active lane skip the column; inside, inactive
           // lanes compute on row 0 (in bounds) and their result is dropped.
-          if (__builtin_amdgcn_ballot_w64(active) != 0ull) {
+          const uint64_t act = __builtin_amdgcn_ballot_w64(active);
+          if (act != 0ull) {
             ++st_steps;
             const int mm = active ? m : 0;
             const int rc = (int)__umul24((unsigned)mm, (unsigned)RS) + qo[c];
@@ -317,11 +318,14 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
               const int jp = mm > 0 ? jt[c] : 0, jn = mm < M - 1 ? jt[c] : 0;
               hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
             }
-            const int sb = (int)__builtin_amdgcn_ubfe(own, (unsigned)qb[c], 1u);
-            const int d = sb ? hs : -hs;  // s_i * h_eff_i; flipping costs 2d
+            // d = s_i * h_eff_i (flipping costs 2d): with dn = -1 for a spin
+            // down and 0 for up, d = (hs ^ dn) - dn
+            const int dn = __builtin_amdgcn_sbfe((int)~own, (unsigned)qb[c], 1u);
+            const int d = (hs ^ dn) - dn;
             const uint32_t u = mt_temper(u0);
-            const bool flip = active & (u <= thw[d > 0 ? d : 0]);
-            const uint64_t fl = __builtin_amdgcn_ballot_w64(flip);
+            const bool le = u <= thw[d > 0 ? d : 0];
+            const uint64_t fl = __builtin_amdgcn_ballot_w64(le) & act;
+            const bool flip = le && active;
             st_flip += fl != 0ull;
             if (wave_walker) nfl_w += (uint32_t)__builtin_popcountll(fl);
             else nfl += flip ? 1 : 0;

@@ -68,6 +68,14 @@ def lib():
         L.orc_exp_approx.restype = C.c_float
         L.orc_approx_threshold.argtypes = [C.c_double, i32, i32]
         L.orc_approx_threshold.restype = u32
+        L.orc_approx_threshold_x.argtypes = [C.c_double, i32]
+        L.orc_approx_threshold_x.restype = u32
+        L.orc_set_two_field.argtypes = [P, P, i32, P, P]
+        L.orc_set_two_field.restype = i32
+        L.orc_bond_of.argtypes = [P, i32]
+        L.orc_bond_of.restype = i64
+        L.orc_get_bond.argtypes = [P, P]
+        L.orc_get_tau_fields.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -83,6 +91,35 @@ def exp_approx(x, kind):
 
 def approx_threshold(beta, d, kind):
     return int(lib().orc_approx_threshold(float(beta), int(d), int(kind)))
+
+
+def approx_threshold_x(x, kind):
+    """Threshold of the approximate flip test for a real cost change 2x (two-field form)."""
+    return int(lib().orc_approx_threshold_x(float(x), int(kind)))
+
+
+def trotter_weights(beta, M, gamma):
+    """Slot weights of the two-field form for a transverse field gamma, M slices.
+
+    Suzuki-Trotter reading: a slice carries the classical cost at inverse
+    temperature beta / M, and neighbouring copies of a spin are coupled by
+    c = -1/2 ln tanh(beta gamma / M) (so that e^{c} + e^{-c} sigma_x is
+    proportional to exp(beta gamma sigma_x / M)).  Returns (a, c) arrays.
+    """
+    beta = np.asarray(beta, np.float64)
+    a = beta / float(M)
+    c = -0.5 * np.log(np.tanh(beta * float(gamma) / float(M)))
+    return a, c
+
+
+def tau_edge_mask(system) -> np.ndarray:
+    """Flags of the tau edges in the edge order of ``system.expand()`` (in-slice
+    edges slice by slice, then the tau edges)."""
+    N, u, v, J, h = system.expand()
+    n_space = int(system.eu.shape[0]) * system.M
+    m = np.zeros(len(u), np.uint8)
+    m[n_space:] = 1
+    return m
 
 
 def _ptr(a: np.ndarray):
@@ -186,6 +223,31 @@ class Chain:
     def set_spins(self, w, s):
         s = np.ascontiguousarray(s, np.int8)
         lib().orc_set_spins(self._c, w, _ptr(s))
+
+    def set_two_field(self, is_tau, a, c):
+        """Switch to the two-field form: tau edges flagged by is_tau (edge order of the
+        constructor), slot weights a[K], c[K]."""
+        t = np.ascontiguousarray(is_tau, np.uint8)
+        a_ = np.ascontiguousarray(a, np.float64)
+        c_ = np.ascontiguousarray(c, np.float64)
+        assert len(a_) == self.K and len(c_) == self.K
+        self._keep += [t, a_, c_]
+        if lib().orc_set_two_field(self._c, _ptr(t), len(t), _ptr(a_), _ptr(c_)) != 0:
+            raise ValueError("oracle rejected the two-field form")
+        return self
+
+    def bond(self):
+        out = np.empty(self.K, np.int64)
+        lib().orc_get_bond(self._c, _ptr(out))
+        return out
+
+    def bond_of(self, w):
+        return int(lib().orc_bond_of(self._c, w))
+
+    def tau_fields(self):
+        out = np.empty((self.K, self.N), np.int32)
+        lib().orc_get_tau_fields(self._c, _ptr(out))
+        return out
 
     def set_acceptance(self, kind):
         """Flip test: ACCEPT_EXACT (exp), ACCEPT_FAST or ACCEPT_ACCURATE (Sec. 2.4 approximations)."""

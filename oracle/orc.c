@@ -16,6 +16,10 @@
  * swap rounds alternate even and odd pairs, each pair consumes one draw of its
  * system's swap generator, and a swap is accepted when Delta >= 0 or
  * u 2^-32 < exp(Delta), Delta = (beta_k - beta_k+1)(E_k - E_k+1).
+ * Two-field form (the QMC models' separate in-slice and tau fields): slot k
+ * carries weights (a_k, c_k) and a state s the log weight -a_k E_sp + c_k B;
+ * a flip is taken when x = a d_sp + c d_t <= 0, else when u 2^-32 < exp(-2x);
+ * swaps use the log ratio of the exchanged assignment in the same weights.
  */
 #include "orc.h"
 
@@ -83,6 +87,13 @@ struct orc_chain {
   uint64_t *flips, *sw_att, *sw_acc, near;
   int64_t sweeps, rounds;
   int32_t accept_kind; /* ORC_ACCEPT_EXACT / _FAST / _ACCURATE */
+  int32_t *ce;         /* input edge of each adjacency entry */
+  /* two-field form (off until orc_set_two_field) */
+  int32_t two_field;
+  uint8_t *ctau;       /* adjacency entry is a tau edge */
+  int32_t *htau;       /* [K][N] tau field; heff then holds the in-slice field (with h) */
+  int64_t *B;          /* [K] sum over tau edges of J s s' */
+  double *wa, *wc;     /* [K] slot weights */
 };
 
 static void recompute(orc_chain *c, int32_t w) {
@@ -90,11 +101,31 @@ static void recompute(orc_chain *c, int32_t w) {
   int8_t *s = c->s + (size_t)w * N;
   int32_t *he = c->heff + (size_t)w * N;
   for (int32_t i = 0; i < N; i++) {
-    int32_t f = c->h[i];
-    for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) f += c->cj[e] * s[c->ci[e]];
+    int32_t f = c->h[i], ft = 0;
+    for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) {
+      if (c->two_field && c->ctau[e])
+        ft += c->cj[e] * s[c->ci[e]];
+      else
+        f += c->cj[e] * s[c->ci[e]];
+    }
     he[i] = f;
+    if (c->two_field) c->htau[(size_t)w * N + i] = ft;
   }
   c->E[w] = orc_energy_of(c, w);
+  if (c->two_field) c->B[w] = orc_bond_of(c, w);
+}
+
+int64_t orc_bond_of(const orc_chain *c, int32_t w) {
+  if (!c->two_field) return 0;
+  const int32_t N = c->N;
+  const int8_t *s = c->s + (size_t)w * N;
+  int64_t b = 0;
+  for (int32_t i = 0; i < N; i++)
+    for (int32_t k = c->rp[i]; k < c->rp[i + 1]; k++) {
+      int32_t j = c->ci[k];
+      if (j > i && c->ctau[k]) b += (int64_t)c->cj[k] * s[i] * s[j];
+    }
+  return b;
 }
 
 int64_t orc_energy_of(const orc_chain *c, int32_t w) {
@@ -123,6 +154,7 @@ orc_chain *orc_new(int32_t N, int32_t nE, const int32_t *u, const int32_t *v, co
   c->rp = (int32_t *)calloc((size_t)N + 1, sizeof(int32_t));
   c->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * nE + 1));
   c->cj = (int8_t *)malloc((size_t)(2 * nE + 1));
+  c->ce = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * nE + 1));
   for (int32_t e = 0; e < nE; e++) {
     c->rp[u[e] + 1]++;
     c->rp[v[e] + 1]++;
@@ -132,8 +164,10 @@ orc_chain *orc_new(int32_t N, int32_t nE, const int32_t *u, const int32_t *v, co
   for (int32_t e = 0; e < nE; e++) {
     int32_t a = u[e], b = v[e];
     c->ci[c->rp[a] + fill[a]] = b;
+    c->ce[c->rp[a] + fill[a]] = e;
     c->cj[c->rp[a] + fill[a]++] = J[e];
     c->ci[c->rp[b] + fill[b]] = a;
+    c->ce[c->rp[b] + fill[b]] = e;
     c->cj[c->rp[b] + fill[b]++] = J[e];
   }
   free(fill);
@@ -178,6 +212,12 @@ void orc_free(orc_chain *c) {
   free(c->flips);
   free(c->sw_att);
   free(c->sw_acc);
+  free(c->ce);
+  free(c->ctau);
+  free(c->htau);
+  free(c->B);
+  free(c->wa);
+  free(c->wc);
   free(c);
 }
 
@@ -223,11 +263,98 @@ uint32_t orc_approx_threshold(double beta, int32_t d, int32_t kind) {
   return (uint32_t)t;
 }
 
+/* The same for a real cost change 2x (the two-field form): p = approx(-2x). */
+uint32_t orc_approx_threshold_x(double x, int32_t kind) {
+  const float p = orc_exp_approx((float)(-2.0 * x), kind);
+  const double t = ceil((double)p * 4294967296.0) - 1.0;
+  if (t < 0.0) return 0u;
+  if (t > 4294967295.0) return 4294967295u;
+  return (uint32_t)t;
+}
+
 void orc_set_acceptance(orc_chain *c, int32_t kind) { c->accept_kind = kind; }
+
+/* ------------------------------------------------------------------------ */
+/* Two-field form (Sec. 2.1-2.2: the QMC models keep a field over the       */
+/* in-slice edges, h_eff_space, and one over the two tau edges of a spin,   */
+/* h_eff_tau, updated by the edge-type switch of Figs. 2 and 3).  Slot k    */
+/* weighs a state s by exp(-a_k E_sp(s) + c_k B(s)): E_sp the cost of h and */
+/* the in-slice edges, B the sum over tau edges of J s s'.  Flipping spin i */
+/* changes the log weight by -2x, x = a d_sp + c d_t, d_sp = s_i             */
+/* h_eff_space_i, d_t = s_i h_eff_tau_i.                                     */
+/* ------------------------------------------------------------------------ */
+int32_t orc_set_two_field(orc_chain *c, const uint8_t *is_tau, int32_t nE, const double *a,
+                          const double *cw) {
+  if (!is_tau || !a || !cw) return -1;
+  const int32_t n_adj = c->rp[c->N];
+  for (int32_t e = 0; e < n_adj; e++)
+    if (c->ce[e] < 0 || c->ce[e] >= nE) return -1;
+  free(c->ctau);
+  free(c->htau);
+  free(c->B);
+  free(c->wa);
+  free(c->wc);
+  c->ctau = (uint8_t *)malloc((size_t)n_adj + 1);
+  for (int32_t e = 0; e < n_adj; e++) c->ctau[e] = is_tau[c->ce[e]] ? 1 : 0;
+  c->htau = (int32_t *)calloc((size_t)c->K * c->N, sizeof(int32_t));
+  c->B = (int64_t *)calloc((size_t)c->K, sizeof(int64_t));
+  c->wa = (double *)malloc(sizeof(double) * (size_t)c->K);
+  c->wc = (double *)malloc(sizeof(double) * (size_t)c->K);
+  memcpy(c->wa, a, sizeof(double) * (size_t)c->K);
+  memcpy(c->wc, cw, sizeof(double) * (size_t)c->K);
+  c->two_field = 1;
+  for (int32_t w = 0; w < c->K; w++) recompute(c, w);
+  return 0;
+}
+
+/* Fig. 1 with the two fields: one draw per spin; accept when x <= 0, else
+ * when the uniform is below exp(-2x); after a flip, each incident edge
+ * updates the neighbour's tau or in-slice field (Figs. 2 and 3). */
+static void sweep_walker_two_field(orc_chain *c, int32_t w) {
+  const int32_t N = c->N;
+  int8_t *s = c->s + (size_t)w * N;
+  int32_t *hs = c->heff + (size_t)w * N;
+  int32_t *ht = c->htau + (size_t)w * N;
+  const int32_t k = c->temp_of[w];
+  const double a = c->wa[k], cw = c->wc[k];
+  orc_mt *g = &c->mt[w];
+  for (int32_t i = 0; i < N; i++) {
+    const uint32_t u = orc_mt_next(g); /* one draw per spin */
+    int32_t d_sp = s[i] * hs[i];
+    int32_t d_t = s[i] * ht[i];
+    double x_sp = a * (double)d_sp;
+    double x_t = cw * (double)d_t;
+    double x = x_sp + x_t; /* the log weight changes by -2x */
+    int accept;
+    if (x <= 0.0) {
+      accept = 1;
+    } else if (c->accept_kind == ORC_ACCEPT_EXACT) {
+      double uniform = (double)u * 0x1p-32;
+      accept = uniform < exp(-2.0 * x);
+    } else {
+      accept = u <= orc_approx_threshold_x(x, c->accept_kind);
+    }
+    if (accept) {
+      int32_t two_s = 2 * s[i]; /* old spin value */
+      for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) {
+        int32_t *field = c->ctau[e] ? ht : hs;
+        field[c->ci[e]] -= two_s * c->cj[e];
+      }
+      s[i] = (int8_t)-s[i];
+      c->E[w] += 2 * (d_sp + d_t);
+      c->B[w] -= 2 * d_t;
+      c->flips[w]++;
+    }
+  }
+}
 
 /* Fig. 1: for each spin in order, draw a uniform; flip if it is below the
  * flip probability; after a flip update the local fields of the neighbours. */
 static void sweep_walker(orc_chain *c, int32_t w) {
+  if (c->two_field) {
+    sweep_walker_two_field(c, w);
+    return;
+  }
   const int32_t N = c->N;
   int8_t *s = c->s + (size_t)w * N;
   int32_t *he = c->heff + (size_t)w * N;
@@ -263,6 +390,14 @@ void orc_swap_round(orc_chain *c, int32_t parity) {
   for (int32_t k = parity & 1; k + 1 < c->K; k += 2) {
     int32_t a = c->walker_at[k], b = c->walker_at[k + 1];
     double delta = (c->beta[k] - c->beta[k + 1]) * (double)(c->E[a] - c->E[b]);
+    if (c->two_field) {
+      /* log ratio of the exchanged to the current assignment:
+       * (a_k - a_k+1)(Esp_a - Esp_b) - (c_k - c_k+1)(B_a - B_b), Esp = E + B */
+      int64_t esp_a = c->E[a] + c->B[a], esp_b = c->E[b] + c->B[b];
+      double d_sp = (c->wa[k] - c->wa[k + 1]) * (double)(esp_a - esp_b);
+      double d_t = (c->wc[k] - c->wc[k + 1]) * (double)(c->B[a] - c->B[b]);
+      delta = d_sp - d_t;
+    }
     uint32_t u = orc_mt_next(&c->swap);
     double uniform = (double)u * 0x1p-32;
     double p = exp(delta);
@@ -372,11 +507,18 @@ int64_t orc_check_fields(const orc_chain *c) {
     const int8_t *s = c->s + (size_t)w * N;
     const int32_t *he = c->heff + (size_t)w * N;
     for (int32_t i = 0; i < N; i++) {
-      int32_t f = c->h[i];
-      for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) f += c->cj[e] * s[c->ci[e]];
+      int32_t f = c->h[i], ft = 0;
+      for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) {
+        if (c->two_field && c->ctau[e])
+          ft += c->cj[e] * s[c->ci[e]];
+        else
+          f += c->cj[e] * s[c->ci[e]];
+      }
       if (f != he[i]) bad++;
+      if (c->two_field && ft != c->htau[(size_t)w * N + i]) bad++;
     }
     if (orc_energy_of(c, w) != c->E[w]) bad++;
+    if (c->two_field && orc_bond_of(c, w) != c->B[w]) bad++;
   }
   return bad;
 }
@@ -384,4 +526,15 @@ int64_t orc_check_fields(const orc_chain *c) {
 void orc_set_spins(orc_chain *c, int32_t w, const int8_t *s) {
   memcpy(c->s + (size_t)w * c->N, s, (size_t)c->N);
   recompute(c, w);
+}
+
+void orc_get_bond(const orc_chain *c, int64_t *out) {
+  for (int32_t w = 0; w < c->K; w++) out[w] = c->two_field ? c->B[w] : 0;
+}
+void orc_get_tau_fields(const orc_chain *c, int32_t *out) {
+  const size_t n = (size_t)c->K * c->N;
+  if (c->two_field)
+    memcpy(out, c->htau, sizeof(int32_t) * n);
+  else
+    memset(out, 0, sizeof(int32_t) * n);
 }

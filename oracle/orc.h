@@ -85,6 +85,18 @@ void orc_set_acceptance(orc_chain *c, int32_t kind);
 float orc_exp_approx(float x, int32_t kind);
 uint32_t orc_approx_threshold(double beta, int32_t d, int32_t kind);
 
+/* Two-field form (Sec. 2.1-2.2): edges flagged in is_tau[nE] (orc_new's edge
+ * order) feed a separate tau field; slot k weighs a state by
+ * exp(-a[k] E_sp + c[k] B), E_sp = cost of h and the other edges, B = sum
+ * over tau edges of J s s'.  Recomputes the fields and B; returns 0, or -1 on
+ * bad input.  orc_get_fields then returns the in-slice field (with h). */
+int32_t orc_set_two_field(orc_chain *c, const uint8_t *is_tau, int32_t nE, const double *a,
+                          const double *cw);
+uint32_t orc_approx_threshold_x(double x, int32_t kind);
+int64_t orc_bond_of(const orc_chain *c, int32_t w);
+void orc_get_bond(const orc_chain *c, int64_t *out);        /* [K] running B */
+void orc_get_tau_fields(const orc_chain *c, int32_t *out);  /* [K][N] */
+
 #ifdef __cplusplus
 }
 #endif

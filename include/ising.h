@@ -147,6 +147,8 @@ typedef struct {
   uint64_t *swap_acc;  /* [slots] acceptances */
   uint64_t *stats;     /* [ISING_N_STATS]: see ising_stats */
   uint64_t *wsteps;    /* [R][2] per walker: wavefront steps with an active spin, with a flip */
+  int32_t *bond;       /* [R] tau-bond sum B = sum over tau edges of J_tau s s' (kept current by
+                          ising_init_state, ising_refresh_energies and two-field sweeps) */
   int64_t sweeps;      /* host: sweeps done (set by the library) */
   int64_t rounds;      /* host: swap rounds done */
 } ising_state;
@@ -164,8 +166,8 @@ enum {
 };
 
 /* Element counts: [spins, mt, energy, temp_of, walker_at, swap_mt, flips,
- * swap_att, swap_acc, stats, wsteps]. */
-#define ISING_STATE_NARRAYS 11
+ * swap_att, swap_acc, stats, wsteps, bond]. */
+#define ISING_STATE_NARRAYS 12
 int32_t ising_state_sizes(const ising_graph *g, int64_t *counts);
 
 /* Seed every walker stream (MT19937 init_genrand with walker_seeds[r]) and
@@ -217,9 +219,51 @@ int32_t ising_record_slots(const ising_graph *g, const ising_state *st, int32_t 
  * counters on the device; synchronises `stream`).                           */
 int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, void *stream);
 
-/* Observables per walker into device int32 obs[R][4]: cost recomputed from the
- * spins, magnetisation sum_i s_i, running cost, temperature slot.            */
+/* Observables per walker into device int32 obs[R][6]: cost recomputed from the
+ * spins, magnetisation sum_i s_i, running cost, temperature slot, tau-bond sum
+ * B recomputed from the spins, running B.                                     */
 int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *obs, void *stream);
+/* Recompute every walker's running cost and tau-bond sum from its spins. */
+int32_t ising_refresh_energies(const ising_graph *g, ising_state *st, void *stream);
+
+/* ---- two-field form --------------------------------------------------------
+ * The paper's QMC models keep two local fields per spin (Sections 2.1-2.2,
+ * Figures 2, 3 and 6): h_eff_space over the in-slice edges (with h) and
+ * h_eff_tau over the two tau edges, and the two are weighted differently.  In
+ * this form slot k carries weights (a_k, c_k) and weighs a walker's state s by
+ * exp(-a_k E_sp(s) + c_k B(s)), E_sp = -sum h s - sum over in-slice edges of
+ * J s s' (all slices), B = sum over tau edges of J_tau s s'; so E = E_sp - B.
+ *   - A flip of spin i with d_sp = s_i h_eff_space_i and d_t = s_i h_eff_tau_i
+ *     changes the log weight by -2x, x = a d_sp + c d_t (IEEE double, the two
+ *     products rounded separately); it is accepted iff x <= 0 or
+ *     u < ceil(2^32 exp(-2x)), i.e. u * 2^-32 < exp(-2x).  Under
+ *     ISING_ACCEPT_FAST / _ACCURATE the probability is the Figure 7
+ *     approximation at -2x rounded to FP32, as for the one-field test.
+ *   - Swap rounds: delta = (a_k - a_k+1)(E_sp,a - E_sp,b) - (c_k - c_k+1)(B_a - B_b)
+ *     (IEEE double, products rounded separately), accepted iff delta >= 0 or
+ *     u * 2^-32 < exp(delta); one draw per pair as before.
+ *   - The running cost E stays the full cost f(s); st->bond holds B.
+ * Thresholds are precomputed per slot over (d_sp, d_t), so the sweep makes the
+ * same integer comparison as the one-field form.  Supported for grids of K4,4
+ * cells with rows of (2 ds + 1)(2 dt + 1) <= 1024 words (ds = max |h| +
+ * sum |J in-slice| of a spin, dt = max sum |J_tau|); swaps then run in their
+ * own kernel; cell moves are refused while the form is on.
+ *
+ * ising_set_two_field: a[slots], c[slots] (host) switch the graph to the form
+ * (both NULL: back to the one-field form).  Needs 2(|a| ds + |c| dt) <= 700 per
+ * slot (ISING_E_RANGE otherwise).  Launch shapes return to their defaults.
+ * States whose B may be stale (after one-field sweeps or cell moves) need
+ * ising_refresh_energies first.  Synchronises `stream`.                      */
+int32_t ising_set_two_field(ising_graph *g, const double *a, const double *c, void *stream);
+/* Host only: the two-field threshold row of one slot, entry
+ * (d_sp + ds)(2 dt + 1) + d_t + dt for |d_sp| <= ds, |d_t| <= dt;
+ * 0xffffffff where x <= 0. */
+int32_t ising_two_field_row(double a, double c, int32_t ds, int32_t dt, int32_t kind, uint32_t *thr);
+/* Host only: Suzuki-Trotter weights of a transverse field gamma over M slices
+ * (a reading: the paper does not print them): a_k = beta_k / M and
+ * c_k = -1/2 ln tanh(beta_k gamma / M), so that neighbouring copies of a spin
+ * carry the transfer factor exp(c s s').                                     */
+int32_t ising_trotter_weights(const double *beta, int32_t n, int32_t M, double gamma, double *a, double *c);
 
 /* ---- learned cell proposal --------------------------------------------------
  * An extension of the method (the paper has no learned part): a unit cell of

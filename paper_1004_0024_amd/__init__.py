@@ -24,4 +24,6 @@ from .binding import (  # noqa: F401
     lib_path,
     level_offsets,
     threshold_row,
+    trotter_weights,
+    two_field_row,
 )

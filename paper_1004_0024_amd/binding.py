@@ -34,7 +34,7 @@ class StateStruct(C.Structure):
         ("spins", C.c_void_p), ("mt", C.c_void_p), ("energy", C.c_void_p), ("temp_of", C.c_void_p),
         ("walker_at", C.c_void_p), ("swap_mt", C.c_void_p), ("flips", C.c_void_p),
         ("swap_att", C.c_void_p), ("swap_acc", C.c_void_p), ("stats", C.c_void_p), ("wsteps", C.c_void_p),
-        ("sweeps", C.c_int64), ("rounds", C.c_int64),
+        ("bond", C.c_void_p), ("sweeps", C.c_int64), ("rounds", C.c_int64),
     ]
 
 
@@ -85,6 +85,10 @@ def lib():
             "ising_heatbath_cells": ([P, P, C.c_uint64, i64, P, P], i32),
             "ising_acceptance_row": ([C.c_double, i32, i32, P], i32),
             "ising_set_acceptance": ([P, i32, P], i32),
+            "ising_refresh_energies": ([P, P, P], i32),
+            "ising_set_two_field": ([P, P, P, P], i32),
+            "ising_two_field_row": ([C.c_double, C.c_double, i32, i32, i32, P], i32),
+            "ising_trotter_weights": ([P, i32, i32, C.c_double, P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -133,6 +137,22 @@ def acceptance_row(beta: float, dmax: int, kind: int) -> np.ndarray:
     out = np.zeros(dmax + 1, np.uint32)
     _check(lib().ising_acceptance_row(C.c_double(beta), int(dmax), int(kind), _np_ptr(out)))
     return out
+
+
+def two_field_row(a: float, c: float, ds: int, dt: int, kind: int = ACCEPT_EXACT) -> np.ndarray:
+    """Two-field threshold row of one slot (host only): [2 ds + 1, 2 dt + 1] over (d_sp, d_t)."""
+    out = np.zeros((2 * ds + 1) * (2 * dt + 1), np.uint32)
+    _check(lib().ising_two_field_row(C.c_double(a), C.c_double(c), int(ds), int(dt), int(kind), _np_ptr(out)))
+    return out.reshape(2 * ds + 1, 2 * dt + 1)
+
+
+def trotter_weights(beta, M: int, gamma: float):
+    """Slot weights (a, c) of a transverse field gamma over M slices (host only)."""
+    b = np.ascontiguousarray(beta, np.float64)
+    a = np.zeros_like(b)
+    c = np.zeros_like(b)
+    _check(lib().ising_trotter_weights(_np_ptr(b), int(b.shape[0]), int(M), C.c_double(gamma), _np_ptr(a), _np_ptr(c)))
+    return a, c
 
 
 def level_offsets(system):
@@ -198,6 +218,16 @@ class Graph:
         """Flip-test variant for later sweeps: ACCEPT_EXACT, ACCEPT_FAST or ACCEPT_ACCURATE."""
         _check(lib().ising_set_acceptance(self.handle, int(kind), _stream()))
 
+    def set_two_field(self, a=None, c=None):
+        """Two-field form with slot weights a[slots], c[slots] (None, None: one-field form)."""
+        if a is None and c is None:
+            _check(lib().ising_set_two_field(self.handle, None, None, _stream()))
+            return
+        a_ = np.ascontiguousarray(a, np.float64)
+        c_ = np.ascontiguousarray(c, np.float64)
+        assert a_.shape == (self.slots,) and c_.shape == (self.slots,)
+        _check(lib().ising_set_two_field(self.handle, _np_ptr(a_), _np_ptr(c_), _stream()))
+
     def set_launch(self, bucket, tpw, walkers_per_group):
         _check(lib().ising_set_launch(self._handle, int(bucket), int(tpw), int(walkers_per_group), _stream()))
 
@@ -215,17 +245,17 @@ class State:
     """Chain state in torch device tensors, walker-major."""
 
     _FIELDS = ["spins", "mt", "energy", "temp_of", "walker_at", "swap_mt", "flips", "swap_att", "swap_acc",
-               "stats", "wsteps"]
+               "stats", "wsteps", "bond"]
 
     def __init__(self, graph: Graph):
         import torch
         self.graph = graph
-        counts = np.zeros(11, np.int64)
+        counts = np.zeros(len(self._FIELDS), np.int64)
         _check(lib().ising_state_sizes(graph.handle, _np_ptr(counts)))
         dev = graph.tables.device
         dt = {"spins": torch.int32, "mt": torch.int32, "energy": torch.int32, "temp_of": torch.int32,
               "walker_at": torch.int32, "swap_mt": torch.int32, "flips": torch.int64, "swap_att": torch.int64,
-              "swap_acc": torch.int64, "stats": torch.int64, "wsteps": torch.int64}
+              "swap_acc": torch.int64, "stats": torch.int64, "wsteps": torch.int64, "bond": torch.int32}
         self.t = {}
         for name, n in zip(self._FIELDS, counts):
             self.t[name] = torch.zeros(max(int(n), 1), dtype=dt[name], device=dev)
@@ -292,6 +322,10 @@ class State:
         _check(lib().ising_heatbath_cells(self.graph.handle, C.byref(self._s), C.c_uint64(key), int(pass_index),
                                           C.c_void_p(moves.data_ptr()) if moves is not None else None, _stream()))
 
+    def refresh_energies(self):
+        """Recompute the running cost and tau-bond sum of every walker from its spins."""
+        _check(lib().ising_refresh_energies(self.graph.handle, C.byref(self._s), _stream()))
+
     def swap(self, parity):
         _check(lib().pt_swap(self.graph.handle, C.byref(self._s), int(parity), _stream()))
 
@@ -305,7 +339,7 @@ class State:
 
     def observables(self):
         import torch
-        obs = torch.zeros((self.graph.R, 4), dtype=torch.int32, device=self.graph.tables.device)
+        obs = torch.zeros((self.graph.R, 6), dtype=torch.int32, device=self.graph.tables.device)
         _check(lib().ising_observables(self.graph.handle, C.byref(self._s), C.c_void_p(obs.data_ptr()), _stream()))
         return obs
 

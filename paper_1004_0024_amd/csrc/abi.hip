@@ -90,8 +90,58 @@ extern "C" int32_t ising_acceptance_row(double beta, int32_t dmax, int32_t kind,
   return ISING_OK;
 }
 
+// Threshold of a flip whose log weight change is -2x (two-field form): every
+// flip with x <= 0 passes; otherwise u <= t  <=>  u * 2^-32 < p, p = exp(-2x)
+// (or the Figure 7 approximation of it, on -2x rounded to FP32).
+static uint32_t two_field_threshold(double x, int32_t kind) {
+  if (x <= 0.0) return 0xffffffffu;
+  if (kind == ISING_ACCEPT_EXACT) {
+    const double t = ceil(ldexp(exp(-2.0 * x), 32));  // 1 .. 2^32 for 0 < 2x <= 700
+    return (uint32_t)((uint64_t)t - 1u);
+  }
+  const float p = exp_fig7((float)(-2.0 * x), kind);
+  const double t = ceil(ldexp((double)p, 32)) - 1.0;
+  return t < 0.0 ? 0u : (t > 4294967295.0 ? 0xffffffffu : (uint32_t)t);
+}
+
+// x = a d_sp + c d_t, the two products rounded separately (no fused multiply-add),
+// the order the swap rule and the sweep's specification use.
+static double two_field_arg(double a, double c, int32_t dsp, int32_t dt) {
+#pragma clang fp contract(off)
+  const double xs = a * (double)dsp;
+  const double xt = c * (double)dt;
+  return xs + xt;
+}
+
+extern "C" int32_t ising_two_field_row(double a, double c, int32_t ds, int32_t dt, int32_t kind, uint32_t *thr) {
+  if (!thr || ds < 0 || dt < 0 || (int64_t)(2 * ds + 1) * (2 * dt + 1) > kMaxTwoFieldRow)
+    return fail(ISING_E_INVAL, "two_field_row: bad arguments");
+  if (kind != ISING_ACCEPT_EXACT && kind != ISING_ACCEPT_FAST && kind != ISING_ACCEPT_ACCURATE)
+    return fail(ISING_E_INVAL, "unknown acceptance kind");
+  if (!isfinite(a) || !isfinite(c)) return fail(ISING_E_RANGE, "two_field_row: weights must be finite");
+  if (2.0 * (fabs(a) * ds + fabs(c) * dt) > 700.0)
+    return fail(ISING_E_RANGE, "two_field_row: 2(|a| ds + |c| dt) exceeds 700");
+  const int32_t wt = 2 * dt + 1;
+  for (int32_t i = -ds; i <= ds; ++i)
+    for (int32_t j = -dt; j <= dt; ++j) thr[(i + ds) * wt + j + dt] = two_field_threshold(two_field_arg(a, c, i, j), kind);
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_trotter_weights(const double *beta, int32_t n, int32_t M, double gamma, double *a,
+                                         double *c) {
+  if (!beta || !a || !c || n < 0 || M < 1) return fail(ISING_E_INVAL, "trotter_weights: bad arguments");
+  if (!(gamma > 0.0) || !isfinite(gamma)) return fail(ISING_E_RANGE, "trotter_weights: gamma must be > 0");
+  for (int32_t k = 0; k < n; ++k) {
+    if (!(beta[k] > 0.0) || !isfinite(beta[k])) return fail(ISING_E_RANGE, "trotter_weights: beta must be > 0");
+    a[k] = beta[k] / (double)M;
+    c[k] = -0.5 * log(tanh(beta[k] * gamma / (double)M));
+  }
+  return ISING_OK;
+}
+
 struct SysHost {
   int32_t S, M, ring, F, deg, dmax, K, cell, FW;
+  int32_t ds = 0, dt = 0;  // two-field bounds: max |h| + sum |J in-slice|, max sum |J_tau| of a spin
   int32_t grid_L = 0, n_phases = 0;
   std::vector<uint16_t> cells;  // cell indices, phase by phase
   int32_t pc[5] = {0, 0, 0, 0, 0};
@@ -150,6 +200,8 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
       bound += std::abs((int32_t)p.second);
     }
     const int32_t jt = M > 1 ? d.J_tau[q] : 0;
+    out.ds = std::max(out.ds, bound);
+    out.dt = std::max(out.dt, ntau * std::abs(jt));
     bound += ntau * std::abs(jt);
     if (bound > ISING_MAX_D)
       return fail(ISING_E_RANGE, "system %d: |h|+sum|J| = %d at spin %d exceeds %d", idx, bound, q, ISING_MAX_D);
@@ -315,11 +367,22 @@ struct ising_graph {
   std::vector<int32_t> walker_sys;
   std::vector<double> slot_beta;  // beta of every slot, in slot order
   bool ladder_all() const {
+    if (two_field) return false;
     for (const Bucket &b : buckets)
       if (!b.ladder) return false;
     return !buckets.empty();
   }
   int32_t accept_kind = ISING_ACCEPT_EXACT;
+  // two-field form: graph-wide bounds of d_sp and d_t, row words (0: rows too long)
+  int32_t qds = 0, qdt = 0, qrow = 0;
+  bool two_field = false;
+  std::vector<double> qa, qc;  // per slot, while the two-field form is on
+  // LDS words of a walker slot for system s in the current form
+  int32_t walker_words(int32_t s) const {
+    const SysInfo &si = sys[s];
+    return two_field ? walker_lds_words(si.S, si.WW, si.fifo_words, si.RS, std::max(qrow, kThrRow), 5)
+                     : walker_lds_words(si.S, si.WW, si.fifo_words, si.RS);
+  }
   DevTables dev{};
   size_t bytes = 0;
   // With several buckets, bucket b > 0 is launched on side[b - 1] (forked from
@@ -336,13 +399,13 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, cellrec, total;
+  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, cellrec, qthr, qa, qc, total;
 };
 
 // Device tables.  Room for one tile per walker, so any launch shape can be
 // installed later without reallocating.
 static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles, int64_t R, int64_t n_cells,
-                         int64_t cell_rows, int64_t n_cellrec) {
+                         int64_t cell_rows, int64_t n_cellrec, int64_t qrow) {
   Layout L{};
   size_t o = 0;
   n_tiles = std::max(n_tiles, R);
@@ -366,13 +429,19 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   o = align256(o + sizeof(int32_t) * std::max<int64_t>(cell_rows / 64, 1));
   L.cellrec = o;
   o = align256(o + sizeof(uint32_t) * std::max<int64_t>(n_cellrec, 1));
+  L.qthr = o;  // two-field threshold rows
+  o = align256(o + sizeof(uint32_t) * std::max<int64_t>(qrow * slots, 1));
+  L.qa = o;
+  o = align256(o + sizeof(double) * slots);
+  L.qc = o;
+  o = align256(o + sizeof(double) * slots);
   L.total = o;
   return L;
 }
 
 // Launch shape of a bucket: `tpw` threads per walker (a power of two; each
 // thread owns ceil(S/tpw) <= 8 columns) and G walkers per workgroup.
-static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
+static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax, bool allow_ladder = true) {
   if (tpw < 1 || (tpw & (tpw - 1)) != 0 || tpw > 1024) return fail(ISING_E_RANGE, "tpw must be a power of two <= 1024");
   const int32_t need = (b.S + tpw - 1) / tpw;
   int32_t cpt = 1;
@@ -385,8 +454,8 @@ static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
   if (lds > 160 * 1024) return fail(ISING_E_RANGE, "launch shape needs %zu bytes of LDS (> 160 KiB)", lds);
   // A workgroup that holds whole systems (G >= Kmax) runs their swap rounds
   // itself when the swap state fits next to the walkers.
-  const bool ladder =
-      G >= Kmax && Kmax <= 256 && tpw <= 64 && lds + (size_t)kLadderWords * 4 <= 160 * 1024;
+  const bool ladder = allow_ladder && G >= Kmax && Kmax <= 256 && tpw <= 64 &&
+                      lds + (size_t)kLadderWords * 4 <= 160 * 1024;
   if (ladder) lds += (size_t)kLadderWords * 4;
   b.tpw = tpw;
   b.cpt = cpt;
@@ -402,13 +471,14 @@ static int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax) {
 // two columns per thread, up to 256 threads and ~40 KiB of LDS per workgroup.
 // Small systems whose whole ladder fits one workgroup take G = Kmax, so their
 // sweeps and swap rounds run in one launch.
-static void default_shape(int32_t S, int32_t walker_words, int32_t Kmax, int32_t &tpw, int32_t &G) {
+static void default_shape(int32_t S, int32_t walker_words, int32_t Kmax, int32_t &tpw, int32_t &G,
+                          bool allow_ladder = true) {
   int32_t p = 8;
   while (p < S) p <<= 1;
   tpw = p >= 256 ? p / 2 : p;
   G = std::max(1, 256 / tpw);
   while (G > 1 && (size_t)G * walker_words * 4 > 40 * 1024) --G;
-  if (G < Kmax && tpw <= 64 && (int64_t)Kmax * tpw <= 1024 &&
+  if (allow_ladder && G < Kmax && tpw <= 64 && (int64_t)Kmax * tpw <= 1024 &&
       ((size_t)Kmax * walker_words + kLadderWords) * 4 <= 160 * 1024)
     G = Kmax;
 }
@@ -468,6 +538,14 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     for (int32_t k = 0; k < h.K; ++k) g.walker_sys.push_back((int32_t)s);
   }
   if (walker > INT32_MAX || slot > INT32_MAX) return fail(ISING_E_RANGE, "too many walkers");
+  for (const SysHost &h : hs) {
+    g.qds = std::max(g.qds, h.ds);
+    g.qdt = std::max(g.qdt, h.dt);
+  }
+  {
+    const int64_t qr = (int64_t)(2 * g.qds + 1) * (2 * g.qdt + 1);
+    g.qrow = qr <= kMaxTwoFieldRow ? (int32_t)qr : 0;
+  }
   g.R = walker;
   g.slots = slot;
   g.spin_words = word;
@@ -486,9 +564,8 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     b.nx = std::get<3>(kv.first);
     int32_t maxw = 0, Kmax = 1;
     for (int32_t s : kv.second) {
-      const SysInfo &si = g.sys[s];
-      maxw = std::max(maxw, walker_lds_words(si.S, si.WW, si.fifo_words, si.RS));
-      Kmax = std::max(Kmax, si.K);
+      maxw = std::max(maxw, g.walker_words(s));
+      Kmax = std::max(Kmax, g.sys[s].K);
     }
     b.walker_words = maxw;
     int32_t tpw, G;
@@ -526,7 +603,7 @@ extern "C" int32_t ising_graph_bytes(const ising_system_desc *sys, int32_t n_sys
     ncl += (int64_t)h.cells.size();
     ncr += (int64_t)h.cellrec.size();
   }
-  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl, g.cell_rows, ncr).total;
+  *dev_bytes = layout_for(n_sys, ntm, g.slots, (int64_t)g.tiles.size(), g.R, ncl, g.cell_rows, ncr, g.qrow).total;
   return ISING_OK;
 }
 
@@ -550,7 +627,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
     ncl += (int64_t)h.cells.size();
     ncr += (int64_t)h.cellrec.size();
   }
-  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl, g->cell_rows, ncr);
+  Layout L = layout_for(n_sys, ntm, g->slots, (int64_t)g->tiles.size(), g->R, ncl, g->cell_rows, ncr, g->qrow);
   if (bytes < L.total) {
     delete g;
     return fail(ISING_E_SIZE, "dev_tables has %zu bytes, needs %zu", bytes, L.total);
@@ -626,6 +703,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.cells = (const uint16_t *)(base + L.cells);
   g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
   g->dev.cellrec = (const uint32_t *)(base + L.cellrec);
+  g->dev.qthr = (const uint32_t *)(base + L.qthr);
+  g->dev.qa = (const double *)(base + L.qa);
+  g->dev.qc = (const double *)(base + L.qc);
+  g->dev.two_field = 0;
+  g->dev.qrow = g->qrow;
+  g->dev.qwt = 2 * g->qdt + 1;
+  g->dev.qoff = g->qds * (2 * g->qdt + 1) + g->qdt;
   g->bytes = L.total;
   if (g->buckets.size() > 1) {
     for (size_t b = 0; b < g->buckets.size(); ++b) {
@@ -650,6 +734,21 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
 
 extern "C" void ising_free_graph(ising_graph *g) { delete g; }
 
+// Two-field threshold rows of every slot for the current weights and flip-test
+// variant (host -> device, then synchronise).
+static int32_t upload_two_field_rows(ising_graph *g, hipStream_t st) {
+  std::vector<uint32_t> rows((size_t)g->slots * g->qrow);
+  for (int64_t k = 0; k < g->slots; ++k) {
+    const int32_t rc = ising_two_field_row(g->qa[k], g->qc[k], g->qds, g->qdt, g->accept_kind,
+                                           rows.data() + (size_t)k * g->qrow);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.qthr, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+          "two-field rows copy");
+  HIP_TRY(hipStreamSynchronize(st), "two-field rows sync");
+  return ISING_OK;
+}
+
 extern "C" int32_t ising_set_acceptance(ising_graph *g, int32_t kind, void *stream) {
   if (!g) return fail(ISING_E_INVAL, "set_acceptance: NULL graph");
   std::vector<uint32_t> rows((size_t)g->slots * kThrRow);
@@ -662,7 +761,67 @@ extern "C" int32_t ising_set_acceptance(ising_graph *g, int32_t kind, void *stre
           "set_acceptance copy");
   HIP_TRY(hipStreamSynchronize(st), "set_acceptance sync");
   g->accept_kind = kind;
+  if (g->two_field) return upload_two_field_rows(g, st);
   return ISING_OK;
+}
+
+// Launch shapes after a change of the walker slot size: default shape per
+// bucket (tuned shapes are dropped), tiles rebuilt and uploaded.
+static int32_t reshape_all(ising_graph *g, hipStream_t st) {
+  for (size_t bi = 0; bi < g->buckets.size(); ++bi) {
+    Bucket &b = g->buckets[bi];
+    int32_t maxw = 0, Kmax = 1;
+    for (int32_t s : g->bucket_sys[bi]) {
+      maxw = std::max(maxw, g->walker_words(s));
+      Kmax = std::max(Kmax, g->sys[s].K);
+    }
+    b.walker_words = maxw;
+    int32_t tpw, G;
+    default_shape(b.S, maxw, Kmax, tpw, G, !g->two_field);
+    int32_t rc = shape_bucket(b, tpw, G, Kmax, !g->two_field);
+    if (rc) return rc;
+  }
+  g->tiles.clear();
+  for (size_t i = 0; i < g->buckets.size(); ++i) tile_bucket(*g, g->buckets[i], g->bucket_sys[i]);
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size(),
+                         hipMemcpyHostToDevice, st),
+          "reshape tiles");
+  HIP_TRY(hipStreamSynchronize(st), "reshape sync");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_set_two_field(ising_graph *g, const double *a, const double *c, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "set_two_field: NULL graph");
+  hipStream_t st = (hipStream_t)stream;
+  if (!a && !c) {  // back to the one-field form
+    if (!g->two_field) return ISING_OK;
+    g->two_field = false;
+    g->dev.two_field = 0;
+    g->qa.clear();
+    g->qc.clear();
+    return reshape_all(g, st);
+  }
+  if (!a || !c) return fail(ISING_E_INVAL, "set_two_field: give both weight arrays or neither");
+  if (g->qrow == 0)
+    return fail(ISING_E_RANGE, "set_two_field: threshold rows of (2*%d+1)*(2*%d+1) words exceed %d", g->qds, g->qdt,
+                kMaxTwoFieldRow);
+  for (const Bucket &b : g->buckets)
+    if (!b.cell) return fail(ISING_E_RANGE, "set_two_field: every template must be a grid of K4,4 cells");
+  for (int64_t k = 0; k < g->slots; ++k) {
+    if (!isfinite(a[k]) || !isfinite(c[k])) return fail(ISING_E_RANGE, "set_two_field: weight %lld not finite", (long long)k);
+    if (2.0 * (fabs(a[k]) * g->qds + fabs(c[k]) * g->qdt) > 700.0)
+      return fail(ISING_E_RANGE, "set_two_field: slot %lld: 2(|a| d_sp + |c| d_t) may exceed 700", (long long)k);
+  }
+  g->qa.assign(a, a + g->slots);
+  g->qc.assign(c, c + g->slots);
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.qa, a, sizeof(double) * g->slots, hipMemcpyHostToDevice, st), "two-field copy");
+  HIP_TRY(hipMemcpyAsync((void *)g->dev.qc, c, sizeof(double) * g->slots, hipMemcpyHostToDevice, st), "two-field copy");
+  int32_t rc = upload_two_field_rows(g, st);
+  if (rc) return rc;
+  const bool was = g->two_field;
+  g->two_field = true;
+  g->dev.two_field = 1;
+  return was ? ISING_OK : reshape_all(g, st);
 }
 
 extern "C" int32_t ising_n_buckets(const ising_graph *g) { return g ? (int32_t)g->buckets.size() : 0; }
@@ -689,7 +848,7 @@ extern "C" int32_t ising_set_launch(ising_graph *g, int32_t bucket, int32_t tpw,
   Bucket b = g->buckets[bucket];
   int32_t Kmax = 1;
   for (int32_t s : g->bucket_sys[bucket]) Kmax = std::max(Kmax, g->sys[s].K);
-  int32_t rc = shape_bucket(b, tpw, walkers_per_group, Kmax);
+  int32_t rc = shape_bucket(b, tpw, walkers_per_group, Kmax, !g->two_field);
   if (rc) return rc;
   g->buckets[bucket] = b;
   g->tiles.clear();
@@ -732,19 +891,20 @@ extern "C" int32_t ising_state_sizes(const ising_graph *g, int64_t *c) {
   c[8] = g->slots;
   c[9] = ISING_N_STATS;
   c[10] = 2 * g->R;
+  c[11] = g->R;
   return ISING_OK;
 }
 
 static int32_t check_state(const ising_state *st) {
   if (!st || !st->spins || !st->mt || !st->energy || !st->temp_of || !st->walker_at || !st->swap_mt ||
-      !st->flips || !st->swap_att || !st->swap_acc || !st->stats || !st->wsteps)
+      !st->flips || !st->swap_att || !st->swap_acc || !st->stats || !st->wsteps || !st->bond)
     return fail(ISING_E_INVAL, "state has a NULL buffer");
   return ISING_OK;
 }
 
 static DevState dev_state(const ising_state *st) {
   return DevState{st->spins, st->mt, st->energy, st->temp_of, st->walker_at, st->swap_mt,
-                  st->flips, st->swap_att, st->swap_acc, st->stats, st->wsteps};
+                  st->flips, st->swap_att, st->swap_acc, st->stats, st->wsteps, st->bond};
 }
 
 extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *walker_seeds,
@@ -938,7 +1098,7 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
     for (int32_t tpw = 8; tpw <= 1024; tpw <<= 1) {
       for (int32_t G = 1; G <= 32; G <<= 1) {
         Bucket b = orig;
-        if (shape_bucket(b, tpw, G, Kmax) != ISING_OK || b.G != G) continue;
+        if (shape_bucket(b, tpw, G, Kmax, !g->two_field) != ISING_OK || b.G != G) continue;
         if (orig.ladder && !b.ladder) continue;  // keep whole ladders in one workgroup
         g->buckets[bi] = b;
         g->tiles.clear();
@@ -1019,6 +1179,15 @@ extern "C" int32_t ising_observables(const ising_graph *g, const ising_state *st
   return ISING_OK;
 }
 
+extern "C" int32_t ising_refresh_energies(const ising_graph *g, ising_state *st, void *stream) {
+  if (!g) return fail(ISING_E_INVAL, "refresh_energies: NULL graph");
+  int32_t rc = check_state(st);
+  if (rc) return rc;
+  HIP_TRY(launch_observables(g->dev, dev_state(st), (int32_t)g->R, nullptr, 1, (hipStream_t)stream),
+          "observables kernel");
+  return ISING_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Learned cell proposal: network entry points
 // ---------------------------------------------------------------------------
@@ -1076,6 +1245,7 @@ extern "C" int32_t ising_propose_cells(const ising_graph *g, ising_state *st, co
   rc = check_mlp(net);
   if (rc) return rc;
   if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  if (g->two_field) return fail(ISING_E_STATE, "cell moves sample the one-field law: turn the two-field form off");
   if (pass_index < 0 || pass_index > (int64_t)UINT32_MAX) return fail(ISING_E_RANGE, "pass_index must fit 32 bits");
   hipStream_t s = (hipStream_t)stream;
   const DevState d = dev_state(st);
@@ -1091,6 +1261,7 @@ extern "C" int32_t ising_heatbath_cells(const ising_graph *g, ising_state *st, u
   int32_t rc = check_state(st);
   if (rc) return rc;
   if (g->cell_rows == 0) return fail(ISING_E_RANGE, "no system has a grid of 8-spin cells");
+  if (g->two_field) return fail(ISING_E_STATE, "cell moves sample the one-field law: turn the two-field form off");
   if (pass_index < 0 || pass_index > (int64_t)UINT32_MAX) return fail(ISING_E_RANGE, "pass_index must fit 32 bits");
   const DevState d = dev_state(st);
   for (int32_t p = 0; p < g->max_phases; ++p)

@@ -81,8 +81,11 @@ hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32
 // One workgroup per system.  Pairs (k, k+1), k = parity, parity+2, ..., one
 // swap-stream draw each in ascending k; accept iff delta >= 0 or
 // u * 2^-32 < exp(delta), delta = (beta_k - beta_k+1)(E_a - E_b) in IEEE
-// double (the only floating-point decision of the chain).  Temperature labels
-// move; spins and streams stay with their walkers.
+// double (the only floating-point decision of the chain).  In the two-field
+// form slot k weighs a state by exp(-a_k E_sp + c_k B) and delta is the log
+// ratio of the exchanged to the current assignment,
+// (a_k - a_k+1)(E_sp,a - E_sp,b) - (c_k - c_k+1)(B_a - B_b), E_sp = E + B.
+// Temperature labels move; spins and streams stay with their walkers.
 __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int32_t parity,
                                                   int32_t *e_row) {
 #pragma clang fp contract(off)
@@ -106,7 +109,13 @@ __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int3
       const int k = p0 + 2 * i;
       const int a = wat[k], b = wat[k + 1];
       const int ea = St.energy[sy.walker0 + a], eb = St.energy[sy.walker0 + b];
-      const double delta = (T.beta[sy.slot0 + k] - T.beta[sy.slot0 + k + 1]) * (double)(ea - eb);
+      double delta = (T.beta[sy.slot0 + k] - T.beta[sy.slot0 + k + 1]) * (double)(ea - eb);
+      if (T.two_field) {
+        const int ba = St.bond[sy.walker0 + a], bb = St.bond[sy.walker0 + b];
+        const double d_sp = (T.qa[sy.slot0 + k] - T.qa[sy.slot0 + k + 1]) * (double)((ea + ba) - (eb + bb));
+        const double d_t = (T.qc[sy.slot0 + k] - T.qc[sy.slot0 + k + 1]) * (double)(ba - bb);
+        delta = d_sp - d_t;
+      }
       const uint32_t u = mt_temper(buf[kMtN + i]);
       const double x = (double)u * 0x1p-32;
       const double p = exp(delta);
@@ -150,9 +159,10 @@ hipError_t launch_record(const DevTables &t, const DevState &s, int32_t n_sys, i
   return hipGetLastError();
 }
 
-// ---- observables: cost from the spins, magnetisation -----------------------
+// ---- observables: cost from the spins, magnetisation, tau-bond sum ----------
 // f(s) = -sum_i h_i s_i - sum_edges J s s, every edge once: in-slice edges from
-// their lower endpoint, tau edges from slice m to m+1 (and M-1 to 0 on a ring).
+// their lower endpoint, tau edges from slice m to m+1 (and M-1 to 0 on a ring);
+// B = sum over the tau edges of J_tau s s'.
 __global__ void __launch_bounds__(256) observables_kernel(DevTables T, DevState St, int32_t *obs,
                                                           int32_t set_energy) {
   const int r = blockIdx.x;
@@ -160,7 +170,7 @@ __global__ void __launch_bounds__(256) observables_kernel(DevTables T, DevState 
   const int S = sy.S, M = sy.M, RS = sy.RS;
   const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)(r - sy.walker0) * sy.WW;
   auto spin = [&](int m, int q) { return (int)((sp[m * RS + (q >> 5)] >> (q & 31)) & 1u) * 2 - 1; };
-  long long e = 0, mag = 0;
+  long long e = 0, mag = 0, bond = 0;
   const int N = S * M;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int m = i / S, q = i - m * S;
@@ -170,27 +180,36 @@ __global__ void __launch_bounds__(256) observables_kernel(DevTables T, DevState 
     mag += s;
     for (int j = 0; j < ts.deg; ++j)
       if (ts.nbr[j] > q) e -= (long long)ts.J[j] * s * spin(m, ts.nbr[j]);
-    if (M > 1 && (m + 1 < M || sy.ring)) e -= (long long)ts.Jtau * s * spin(m + 1 < M ? m + 1 : 0, q);
+    if (M > 1 && (m + 1 < M || sy.ring)) bond += (long long)ts.Jtau * s * spin(m + 1 < M ? m + 1 : 0, q);
   }
-  __shared__ long long red[2][256];
+  e -= bond;
+  __shared__ long long red[3][256];
   red[0][threadIdx.x] = e;
   red[1][threadIdx.x] = mag;
+  red[2][threadIdx.x] = bond;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       red[0][threadIdx.x] += red[0][threadIdx.x + w];
       red[1][threadIdx.x] += red[1][threadIdx.x + w];
+      red[2][threadIdx.x] += red[2][threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int et = (int)red[0][0];
-    if (set_energy) St.energy[r] = et;
+    const int et = (int)red[0][0], bt = (int)red[2][0];
+    if (set_energy) {
+      St.energy[r] = et;
+      St.bond[r] = bt;
+    }
     if (obs) {
-      obs[(size_t)r * 4 + 0] = et;
-      obs[(size_t)r * 4 + 1] = (int)red[1][0];
-      obs[(size_t)r * 4 + 2] = St.energy[r];
-      obs[(size_t)r * 4 + 3] = St.temp_of[r];
+      int32_t *o = obs + (size_t)r * 6;
+      o[0] = et;
+      o[1] = (int)red[1][0];
+      o[2] = St.energy[r];
+      o[3] = St.temp_of[r];
+      o[4] = bt;
+      o[5] = St.bond[r];
     }
   }
 }

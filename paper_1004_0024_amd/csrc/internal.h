@@ -103,10 +103,17 @@ __host__ __device__ inline int32_t fifo_depth(int32_t f) {
 
 // LDS words of one walker slot: generator ring (+ shadow), uniform queues,
 // spins (M rows of RS words, with one halo row before and one after), threshold
-// row, reduction slots.
-__host__ __device__ inline int32_t walker_lds_words(int32_t S, int32_t WW, int32_t FW, int32_t RS) {
-  return gen_ring_words(S) + kMtN + FW + WW + 2 * RS + kThrRow + 4;
+// row, reduction slots (running cost, flips, wavefront steps, steps with a
+// flip; in the two-field form also the running tau-bond sum).
+__host__ __device__ inline int32_t walker_lds_words(int32_t S, int32_t WW, int32_t FW, int32_t RS,
+                                                    int32_t thr_words = kThrRow, int32_t acc_words = 4) {
+  return gen_ring_words(S) + kMtN + FW + WW + 2 * RS + thr_words + acc_words;
 }
+
+// Two-field form: slot k's threshold row has one entry per pair (d_sp, d_t),
+// d_sp in [-qds, qds] and d_t in [-qdt, qdt], at (d_sp + qds) * (2 qdt + 1) +
+// d_t + qdt; rows longer than this are not supported.
+constexpr int kMaxTwoFieldRow = 1024;
 
 struct DevTables {
   const SysInfo *sys;
@@ -119,6 +126,11 @@ struct DevTables {
   const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
   const int32_t *tile_sys;    // per 64-row tile of cell moves: its system
   const uint32_t *cellrec;    // cell records of the grid templates (see kCellRecWords)
+  // two-field form: per-slot weights (a, c) and threshold rows of qrow words
+  const uint32_t *qthr;       // [slots][qrow]
+  const double *qa, *qc;      // [slots]
+  int32_t two_field;          // 1: sweeps and swaps use the two-field form
+  int32_t qrow, qwt, qoff;    // row words, 2 qdt + 1, qds * qwt + qdt
 };
 
 struct DevState {
@@ -126,6 +138,7 @@ struct DevState {
   int32_t *energy, *temp_of, *walker_at;
   uint32_t *swap_mt;
   uint64_t *flips, *swap_att, *swap_acc, *stats, *wsteps;
+  int32_t *bond;  // running sum over tau edges of J_tau s s' (two-field form)
 };
 
 // Kernel launchers (each returns the hipError_t of the launch).

@@ -37,7 +37,12 @@
 //    g mod depth, where it waits until the column reaches that slice (slot k
 //    of a queue is 64 words after slot k - 1, so a queue sits in one bank and
 //    the 64 columns of a wavefront use 64 different banks);
-//  - the walker's threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1.
+//  - the walker's threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1, or in
+//    the two-field form the row of its slot over (d_sp, d_t).
+// Two-field form (the QMC models' separate fields, Sections 2.1-2.2): the
+// in-slice part of the field (with h) and the tau part are kept apart, d_sp =
+// s h_sp and d_t = s h_tau, and the threshold is looked up at the pair; the
+// walker also tracks its tau-bond sum B, which changes by -2 d_t on a flip.
 // The local field of a spin is pulled from its neighbours' bits when the spin
 // is visited (no field array, no conflicting neighbour updates).  For cell
 // templates (K4,4 unit cells) the four in-cell neighbours are the other nibble
@@ -92,7 +97,7 @@ __device__ void ladder_swap_round(const DevTables &T, const DevState &St, const 
   misc[0] = h;
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER>
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>
 __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, int32_t tile0, int32_t G,
                                                      int32_t TPW, int32_t PW, int32_t n_sweeps,
                                                      int32_t init_mode, LadderArgs la) {
@@ -125,6 +130,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     if (x >= zs) g[x - Zg] = v;
   }
   const int SWW = WW + 2 * RS;  // spin rows with the two halo rows
+  const int TRW = TF ? T.qrow : kThrRow;  // threshold row words
+  constexpr int NACC = TF ? 5 : 4;        // reduction words
   for (int i = tid; i < nw * SWW; i += nthr) {
     const int w = i / SWW, j = i - w * SWW;
     int src = j - RS;  // halo rows: copies of the last and the first slice (ring), else zero
@@ -134,17 +141,24 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         (init_mode || src < 0) ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + src];
   }
   if (!init_mode) {
-    for (int i = tid; i < nw * kThrRow; i += nthr) {
-      const int w = i / kThrRow, j = i - w * kThrRow;
+    const uint32_t *rows = TF ? T.qthr : T.thr;
+    for (int i = tid; i < nw * TRW; i += nthr) {
+      const int w = i / TRW, j = i - w * TRW;
       const int slot = St.temp_of[sy.walker0 + tile.w0 + w];
-      wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + slot) * kThrRow + j];
+      wbase(w)[ZP + FW + SWW + j] = rows[(size_t)(sy.thr0 + slot) * TRW + j];
     }
   }
   // reduction words: running energy (the walker's cost, so a swap round in the
-  // launch can read it), flips, wavefront steps, wavefront steps with a flip
-  for (int i = tid; i < nw * 4; i += nthr)
-    wbase(i / 4)[ZP + FW + SWW + kThrRow + (i & 3)] =
-        ((i & 3) == 0 && !init_mode) ? (uint32_t)St.energy[sy.walker0 + tile.w0 + i / 4] : 0u;
+  // launch can read it), flips, wavefront steps, wavefront steps with a flip,
+  // and in the two-field form the running tau-bond sum
+  for (int i = tid; i < nw * NACC; i += nthr) {
+    const int w = i / NACC, j = i - w * NACC;
+    const int r = sy.walker0 + tile.w0 + w;
+    uint32_t v = 0u;
+    if (!init_mode && j == 0) v = (uint32_t)St.energy[r];
+    if (TF && !init_mode && j == 4) v = (uint32_t)St.bond[r];
+    wbase(w)[ZP + FW + SWW + TRW + j] = v;
+  }
   // ladder tiles (the whole system in this workgroup): swap state in LDS
   const bool ladder = LADDER && la.swap_every > 0 && !init_mode;
   uint32_t *swin = lds + G * PW;
@@ -166,7 +180,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   uint32_t *fq = wb + ZP;
   uint32_t *sp = fq + FW + RS;  // row 0 (halo rows at sp - RS and sp + WW)
   const uint32_t *thw = sp + WW + RS;
-  int32_t *acc = (int32_t *)(thw + kThrRow);
+  int32_t *acc = (int32_t *)(thw + TRW);
+  const int qwt = TF ? T.qwt : 0, qoff = TF ? T.qoff : 0;
 
   int qo[CPT], qb[CPT], base[CPT], jt[CPT], f[CPT], jpack[CPT], fb[CPT], fmask[CPT];
   int xoff[CPT][NX > 0 ? NX : 1], xbit[CPT][NX > 0 ? NX : 1], xj2[CPT][NX > 0 ? NX : 1];
@@ -197,8 +212,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
     jt[c] = ts.Jtau;
     f[c] = col[c] ? (int)ts.f : (1 << 24);  // a column without a spin is never active
-    // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms: the constant part is `base`.
-    base[c] = (int)ts.h - sumJ - (RING ? 2 * (int)ts.Jtau : 0);
+    // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms: the constant part is `base`
+    // (in the two-field form without the tau terms, which form h_tau).
+    base[c] = (int)ts.h - sumJ - (RING && !TF ? 2 * (int)ts.Jtau : 0);
     const uint32_t fw = T.fifo[sy.tmpl0 + qq0];
     fb[c] = (int)(fw >> 8);
     fmask[c] = (1 << (fw & 0xff)) - 1;
@@ -258,6 +274,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 
   int gslot = c0 * S;  // generator slot of the next chunk
   int dE = 0, nfl = 0;  // per lane: sum of d over flips (the cost changes by 2d), flips
+  int dB = 0;           // per lane, two-field form: sum of d_t over flips (B changes by -2 d_t)
   int64_t n_rounds = 0;  // swap rounds run in this launch (ladder tiles)
   uint32_t st_steps = 0, st_flip = 0, nfl_w = 0;  // per wavefront
 
@@ -312,24 +329,42 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
               hs += __builtin_amdgcn_sbfe((int)own_p[xoff[c][j]], (unsigned)xbit[c][j], 1u) & xj2[c][j];
             const int bp = (int)__builtin_amdgcn_ubfe(own_p[-RS], (unsigned)qb[c], 1u);
             const int bn = (int)__builtin_amdgcn_ubfe(own_p[RS], (unsigned)qb[c], 1u);
+            int ht = 0;  // tau part of the field (two-field form)
             if (RING) {
-              hs += 2 * jt[c] * (bp + bn);
+              if (TF)
+                ht = 2 * jt[c] * (bp + bn) - 2 * jt[c];
+              else
+                hs += 2 * jt[c] * (bp + bn);
             } else {
               const int jp = mm > 0 ? jt[c] : 0, jn = mm < M - 1 ? jt[c] : 0;
-              hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
+              if (TF)
+                ht = jp * (2 * bp - 1) + jn * (2 * bn - 1);
+              else
+                hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
             }
             // d = s_i * h_eff_i (flipping costs 2d): with dn = -1 for a spin
             // down and 0 for up, d = (hs ^ dn) - dn
             const int dn = __builtin_amdgcn_sbfe((int)~own, (unsigned)qb[c], 1u);
-            const int d = (hs ^ dn) - dn;
+            int d, dt = 0;
+            uint32_t thv;
+            if (TF) {
+              const int dsp = (hs ^ dn) - dn;
+              dt = (ht ^ dn) - dn;
+              d = dsp + dt;
+              thv = thw[dsp * qwt + dt + qoff];
+            } else {
+              d = (hs ^ dn) - dn;
+              thv = thw[d > 0 ? d : 0];
+            }
             const uint32_t u = mt_temper(u0);
-            const bool le = u <= thw[d > 0 ? d : 0];
+            const bool le = u <= thv;
             const uint64_t fl = __builtin_amdgcn_ballot_w64(le) & act;
             const bool flip = le && active;
             st_flip += fl != 0ull;
             if (wave_walker) nfl_w += (uint32_t)__builtin_popcountll(fl);
             else nfl += flip ? 1 : 0;
             dE += flip ? d : 0;
+            if (TF) dB += flip ? dt : 0;
             if (flip) {
               const uint32_t bit = 1u << qb[c];
               atomicXor(own_p, bit);
@@ -357,12 +392,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         __syncthreads();
         if (tid == 0)
           ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
-                            ZP + FW + SWW + kThrRow);
+                            ZP + FW + SWW + TRW);
         ++n_rounds;
         __syncthreads();
-        for (int i = tid; i < nw * kThrRow; i += nthr) {
-          const int w = i / kThrRow, j = i - w * kThrRow;
-          wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + tof[w]) * kThrRow + j];
+        for (int i = tid; i < nw * TRW; i += nthr) {
+          const int w = i / TRW, j = i - w * TRW;
+          wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + tof[w]) * TRW + j];
         }
         __syncthreads();
       }
@@ -372,6 +407,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   // ---- write back ----
   if (live && !init_mode) {
     atomicAdd(&acc[0], 2 * dE);
+    if (TF && dB) atomicAdd(&acc[4], -2 * dB);
     if (nfl) atomicAdd(&acc[1], nfl);
     // wavefront statistics (and, when a wavefront is one walker's, its flip
     // count) go to the walker of the wavefront's first lane
@@ -394,8 +430,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   }
   if (!init_mode && tid < nw) {
     const int r = sy.walker0 + tile.w0 + tid;
-    const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + SWW + kThrRow);
+    const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + SWW + TRW);
     St.energy[r] = a[0];
+    if (TF) St.bond[r] = a[4];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
     St.wsteps[2 * (size_t)r] += (unsigned long long)(uint32_t)a[2];
     St.wsteps[2 * (size_t)r + 1] += (unsigned long long)(uint32_t)a[3];
@@ -411,10 +448,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   }
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER = false>
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>
 static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bucket &b,
                                  int32_t n_sweeps, int32_t init_mode, hipStream_t st, LadderArgs la) {
-  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER>;
+  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER, TF>;
   // Allow the whole LDS once per instantiation (outside any stream capture
   // after the first launch of a variant).
   static bool lds_limit_set = false;
@@ -429,54 +466,65 @@ static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bu
   return hipGetLastError();
 }
 
-template <int NX, bool CELL, bool RING>
+template <int NX, bool CELL, bool RING, bool TF>
 static hipError_t launch_cpt(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
                              int32_t init_mode, hipStream_t st, LadderArgs la) {
   const bool ws = b.tpw <= 64;
-  if (b.ladder) {  // whole ladders in one workgroup: walkers of at most one wavefront each
-    if (!ws) return hipErrorInvalidValue;
-    switch (b.cpt) {
-      case 1: return launch_variant<NX, CELL, RING, 1, true, true>(t, s, b, n_sweeps, init_mode, st, la);
-      case 2: return launch_variant<NX, CELL, RING, 2, true, true>(t, s, b, n_sweeps, init_mode, st, la);
-      case 4: return launch_variant<NX, CELL, RING, 4, true, true>(t, s, b, n_sweeps, init_mode, st, la);
-      case 8: return launch_variant<NX, CELL, RING, 8, true, true>(t, s, b, n_sweeps, init_mode, st, la);
+  if constexpr (!TF) {
+    if (b.ladder) {  // whole ladders in one workgroup: walkers of at most one wavefront each
+      if (!ws) return hipErrorInvalidValue;
+      switch (b.cpt) {
+        case 1: return launch_variant<NX, CELL, RING, 1, true, true, false>(t, s, b, n_sweeps, init_mode, st, la);
+        case 2: return launch_variant<NX, CELL, RING, 2, true, true, false>(t, s, b, n_sweeps, init_mode, st, la);
+        case 4: return launch_variant<NX, CELL, RING, 4, true, true, false>(t, s, b, n_sweeps, init_mode, st, la);
+        case 8: return launch_variant<NX, CELL, RING, 8, true, true, false>(t, s, b, n_sweeps, init_mode, st, la);
+      }
+      return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
+  } else {
+    if (b.ladder) return hipErrorInvalidValue;  // the two-field form swaps in swap_kernel
   }
   switch (b.cpt) {
-    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 1, false>(t, s, b, n_sweeps, init_mode, st, la);
-    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 2, false>(t, s, b, n_sweeps, init_mode, st, la);
-    case 4: return ws ? launch_variant<NX, CELL, RING, 4, true>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 4, false>(t, s, b, n_sweeps, init_mode, st, la);
-    case 8: return ws ? launch_variant<NX, CELL, RING, 8, true>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 8, false>(t, s, b, n_sweeps, init_mode, st, la);
+    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 1, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 2, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 4: return ws ? launch_variant<NX, CELL, RING, 4, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 4, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 8: return ws ? launch_variant<NX, CELL, RING, 8, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                      : launch_variant<NX, CELL, RING, 8, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
   }
   return hipErrorInvalidValue;
 }
 
-template <bool CELL, bool RING>
+template <bool CELL, bool RING, bool TF>
 static hipError_t launch_nx(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
                             int32_t init_mode, hipStream_t st, LadderArgs la) {
   switch (b.nx) {
-    case 0: return launch_cpt<0, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
-    case 2: return launch_cpt<2, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
-    case 4: return launch_cpt<4, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la);
-    case 6: if (!CELL) return launch_cpt<6, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la); break;
-    case 8: if (!CELL) return launch_cpt<8, CELL, RING>(t, s, b, n_sweeps, init_mode, st, la); break;
+    case 0: return launch_cpt<0, CELL, RING, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 2: return launch_cpt<2, CELL, RING, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 4: return launch_cpt<4, CELL, RING, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 6: if (!CELL) return launch_cpt<6, CELL, RING, TF>(t, s, b, n_sweeps, init_mode, st, la); break;
+    case 8: if (!CELL) return launch_cpt<8, CELL, RING, TF>(t, s, b, n_sweeps, init_mode, st, la); break;
   }
   return hipErrorInvalidValue;
 }
 
+// The initial-spins launch (init_mode) reads no thresholds and writes no
+// energies, so it always takes the one-field variant.
 hipError_t launch_sweep(const DevTables &t, const DevState &s, const Bucket &b, int32_t n_sweeps,
                         int32_t init_mode, hipStream_t st, LadderArgs la) {
   if (b.ntiles == 0) return hipSuccess;
+  if (t.two_field && !init_mode) {
+    if (!b.cell) return hipErrorInvalidValue;  // the two-field form is built for cell templates
+    return b.ring ? launch_nx<true, true, true>(t, s, b, n_sweeps, init_mode, st, la)
+                  : launch_nx<true, false, true>(t, s, b, n_sweeps, init_mode, st, la);
+  }
   if (b.cell)
-    return b.ring ? launch_nx<true, true>(t, s, b, n_sweeps, init_mode, st, la)
-                  : launch_nx<true, false>(t, s, b, n_sweeps, init_mode, st, la);
-  return b.ring ? launch_nx<false, true>(t, s, b, n_sweeps, init_mode, st, la)
-                : launch_nx<false, false>(t, s, b, n_sweeps, init_mode, st, la);
+    return b.ring ? launch_nx<true, true, false>(t, s, b, n_sweeps, init_mode, st, la)
+                  : launch_nx<true, false, false>(t, s, b, n_sweeps, init_mode, st, la);
+  return b.ring ? launch_nx<false, true, false>(t, s, b, n_sweeps, init_mode, st, la)
+                : launch_nx<false, false, false>(t, s, b, n_sweeps, init_mode, st, la);
 }
 
 }  // namespace ising

@@ -158,3 +158,59 @@ def test_acceptance_kind_rejected():
     import paper_1004_0024_amd as pa
     with pytest.raises(pa.IsingError):
         pa.acceptance_row(0.5, 10, 7)
+
+
+def test_two_field_rows_match_the_flip_rule():
+    """Two-field thresholds: entry (d_sp, d_t) is the largest u with u * 2^-32 < exp(-2x),
+    x = a d_sp + c d_t in double (products rounded separately), every u passing at x <= 0;
+    under the Fig. 7 variants the rows equal the oracle's thresholds bit for bit."""
+    import oracle
+    rng = np.random.default_rng(5)
+    ds, dt = 21, 6
+    weights = [(0.05, 0.9), (0.3, 2.1), (0.8, 0.02), (1.5, 0.4)] + \
+        [tuple(rng.uniform(0.01, 2.0, 2)) for _ in range(6)] + [(0.125, 0.125), (-0.2, 0.3)]
+    for a, c in weights:
+        row = pa.two_field_row(a, c, ds, dt, pa.ACCEPT_EXACT)
+        for i in range(-ds, ds + 1):
+            for j in range(-dt, dt + 1):
+                x = a * i + c * j
+                t = int(row[i + ds, j + dt])
+                if x <= 0:
+                    assert t == 0xFFFFFFFF, (a, c, i, j)
+                    continue
+                p = np.exp(-2.0 * x)
+                assert t * 2.0 ** -32 < p and not ((t + 1) * 2.0 ** -32 < p), (a, c, i, j)
+        for kind in (pa.ACCEPT_FAST, pa.ACCEPT_ACCURATE):
+            row = pa.two_field_row(a, c, ds, dt, kind)
+            for i in range(-ds, ds + 1):
+                for j in range(-dt, dt + 1):
+                    x = a * i + c * j
+                    want = 0xFFFFFFFF if x <= 0 else oracle.approx_threshold_x(x, kind)
+                    assert int(row[i + ds, j + dt]) == want, (kind, a, c, i, j)
+    # a = c = beta: the row over d_sp + d_t is the one-field row (dyadic beta: exact products)
+    for beta in (0.125, 0.375, 1.0):
+        row = pa.two_field_row(beta, beta, ds, dt, pa.ACCEPT_EXACT)
+        one = pa.threshold_row(beta, ds + dt)
+        for i in range(-ds, ds + 1):
+            for j in range(-dt, dt + 1):
+                assert row[i + ds, j + dt] == one[max(i + j, 0)], (beta, i, j)
+
+
+def test_two_field_row_rejects_out_of_range():
+    with pytest.raises(pa.IsingError):
+        pa.two_field_row(30.0, 1.0, 21, 6)  # exp(-2x) would underflow
+    with pytest.raises(pa.IsingError):
+        pa.two_field_row(0.5, 0.5, 40, 40)  # row longer than the supported 1024 words
+
+
+def test_trotter_weights_match_oracle():
+    import oracle
+    from gen import beta_ladder
+    beta = beta_ladder(32, 0.1, 3.0)
+    for M, G in ((64, 1.0), (32, 0.3), (8, 2.5)):
+        a, c = pa.trotter_weights(beta, M, G)
+        ra, rc = oracle.trotter_weights(beta, M, G)
+        assert np.array_equal(a, ra)
+        assert np.allclose(c, rc, rtol=2e-15, atol=0), (M, G)  # libm and numpy: a few ulp
+    with pytest.raises(pa.IsingError):
+        pa.trotter_weights(beta, 8, 0.0)

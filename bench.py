@@ -89,6 +89,61 @@ def batch_leg(name, n_sweeps, reps=3):
             "value": g.attempts_per_sweep * n_sweeps / (ms / 1e3), "unit": "spin-flip attempts/s"}
 
 
+def two_field_leg(steps, gamma=1.0):
+    """The throughput workload in the two-field form (the QMC models' separate in-slice
+    and tau fields): every tau coupling +1, Trotter weights of a transverse field gamma
+    over the 64 slices, launch shapes autotuned in this form; `steps` steps of 100
+    sweeps with a swap round after each, HIP events around every sweep launch."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import paper_1004_0024_amd as pa
+    from gen import make_workload
+
+    wl = make_workload("B")
+    wl.systems = [dataclasses.replace(s, J_tau=np.ones(s.S, np.int8)) for s in wl.systems]
+    g = pa.Graph(wl.systems)
+    ab = [pa.trotter_weights(s.beta, s.M, gamma) for s in wl.systems]
+    g.set_two_field(np.concatenate([x[0] for x in ab]), np.concatenate([x[1] for x in ab]))
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    g.autotune(scratch, reps=3)
+    del scratch
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    stream = torch.cuda.current_stream()
+    n_sw = wl.n_sweeps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_sw * steps)]
+    for t in range(n_sw):  # warm-up step
+        st.sweep(1, 0)
+        st.swap(t & 1)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(steps):
+        for t in range(n_sw):
+            evs[2 * (k * n_sw + t)].record(stream)
+            st.sweep(1, 0)
+            evs[2 * (k * n_sw + t) + 1].record(stream)
+            st.swap(t & 1)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    sweep_ms = [evs[2 * i].elapsed_time(evs[2 * i + 1]) for i in range(n_sw * steps)]
+    avg = sum(sweep_ms) / len(sweep_ms)
+    stats = st.stats()
+    achieved = BYTES_PER_ATTEMPT * g.attempts_per_sweep / (avg / 1e3) / 1e9
+    return {"workload": wl.name + ", two-field form (unit tau couplings, gamma %.2f)" % gamma,
+            "steps": steps, "ms_per_step": ms / steps,
+            "value": g.attempts_per_sweep * n_sw * steps / (ms / 1e3), "unit": "spin-flip attempts/s",
+            "sweep_kernel_ms": {"mean": avg, "min": min(sweep_ms), "max": max(sweep_ms)},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT},
+            "launch_shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")} for b in g.buckets()],
+            "flip_rate": stats["flips"] / max(1, stats["attempts"]),
+            "wave_steps_with_flip": stats["wave_flip_steps"] / max(1, stats["wave_steps"])}
+
+
 def learned_leg(ess_steps, train_rows=1 << 20):
     """Learned cell proposal on the 256 x 32-walker, 4,096-spin workload: train the
     network on the GPU from plain-chain samples, then effective samples per second of
@@ -205,6 +260,7 @@ def main():
                     help="also run one device copy of this size (counter calibration)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
     ap.add_argument("--no-batches", action="store_true", help="skip the many-replica and uneven-batch legs")
+    ap.add_argument("--no-two-field", action="store_true", help="skip the two-field (QMC) leg")
     ap.add_argument("--ess-steps", type=int, default=10000,
                     help="chain steps per ESS estimate in the learned-proposal leg")
     args = ap.parse_args()
@@ -275,6 +331,7 @@ def main():
     g1.record(rep.stream)
     rep.stream.synchronize()
     graph_ms = g0.elapsed_time(g1) / max(1, args.steps // 2)
+    stats = st.stats()
     avg_sweep_s = sum(sweep_ms) / len(sweep_ms) / 1e3
     attempts_step = g.attempts_per_sweep * n_sw
     value = attempts_step * args.steps / (ms / 1e3)
@@ -305,10 +362,17 @@ def main():
         "graph_replay": {"ms_per_step": graph_ms, "value": g.attempts_per_sweep * n_sw / (graph_ms / 1e3)},
         "launch_shapes": tuned,
         "sweep_kernel_ms": {"mean": avg_sweep_s * 1e3, "min": min(sweep_ms), "max": max(sweep_ms)},
+        # accepted flips per attempt, and the share of wavefront steps in which some lane
+        # flipped (the analogue of the paper's probability of waiting for a flip)
+        "flip_rate": stats["flips"] / max(1, stats["attempts"]),
+        "wave_steps_with_flip": stats["wave_flip_steps"] / max(1, stats["wave_steps"]),
     }
     del rep, st
     if not args.no_batches:
         out["other_shapes"] = [batch_leg("A", 1000), batch_leg("C", 20), batch_leg("D", 10)]
+    if not args.no_two_field:
+        out["two_field"] = two_field_leg(max(2, args.steps // 2))
+        out["two_field"]["over_one_field"] = out["two_field"]["value"] / value
     if not args.no_learned:
         out["effective_samples"] = learned_leg(args.ess_steps)
     if not args.no_cpu_baseline:

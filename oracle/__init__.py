@@ -76,6 +76,9 @@ def lib():
         L.orc_bond_of.restype = i64
         L.orc_get_bond.argtypes = [P, P]
         L.orc_get_tau_fields.argtypes = [P, P]
+        L.orc_set_pairs.argtypes = [P, i32, i32, P]
+        L.orc_set_pairs.restype = i32
+        L.orc_get_pair_mt.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -235,6 +238,24 @@ class Chain:
         if lib().orc_set_two_field(self._c, _ptr(t), len(t), _ptr(a_), _ptr(c_)) != 0:
             raise ValueError("oracle rejected the two-field form")
         return self
+
+    def set_pairs(self, S, M, pair_seeds):
+        """Switch to the layer-pair order (Sec. 3.2, Fig. 12c): M/2 generators per walker,
+        seeded pair_seeds[w * M/2 + t]; the initial spins are redrawn from them."""
+        ps = np.ascontiguousarray(pair_seeds, np.uint32)
+        assert ps.shape == (self.K * (M // 2),)
+        self._keep.append(ps)
+        if lib().orc_set_pairs(self._c, int(S), int(M), _ptr(ps)) != 0:
+            raise ValueError("oracle rejected the layer-pair order")
+        self.pM = int(M)
+        return self
+
+    def pair_mt(self):
+        n = self.K * (self.pM // 2)
+        win = np.empty((n, 624), np.uint32)
+        used = np.empty(n, np.int64)
+        lib().orc_get_pair_mt(self._c, _ptr(win), _ptr(used))
+        return win, used
 
     def bond(self):
         out = np.empty(self.K, np.int64)

@@ -20,6 +20,10 @@
  * carries weights (a_k, c_k) and a state s the log weight -a_k E_sp + c_k B;
  * a flip is taken when x = a d_sp + c d_t <= 0, else when u 2^-32 < exp(-2x);
  * swaps use the log ratio of the exchanged assignment in the same weights.
+ * Layer-pair order (the paper's GPU layout): slices (2t, 2t+1) of a walker
+ * share generator t; a sweep runs the even slices, then the odd ones, in index
+ * order; the initial spins of slice 2t+j are the top bits of outputs
+ * j*S .. j*S+S-1 of generator t.
  */
 #include "orc.h"
 
@@ -94,6 +98,9 @@ struct orc_chain {
   int32_t *htau;       /* [K][N] tau field; heff then holds the in-slice field (with h) */
   int64_t *B;          /* [K] sum over tau edges of J s s' */
   double *wa, *wc;     /* [K] slot weights */
+  /* layer-pair order (off until orc_set_pairs) */
+  int32_t pairs, pS, pM; /* spins per slice, slices (even) */
+  orc_mt *pmt;           /* [K][M/2] one stream per layer pair */
 };
 
 static void recompute(orc_chain *c, int32_t w) {
@@ -218,6 +225,7 @@ void orc_free(orc_chain *c) {
   free(c->B);
   free(c->wa);
   free(c->wc);
+  free(c->pmt);
   free(c);
 }
 
@@ -348,11 +356,85 @@ static void sweep_walker_two_field(orc_chain *c, int32_t w) {
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Layer-pair order (Sec. 3.2, Fig. 12c): the M slices of a layered system   */
+/* are grouped in pairs (2t, 2t+1), each pair with its own generator; a      */
+/* sweep first visits every even slice, each in index order with draws from  */
+/* its pair's generator, then every odd slice the same way.  Slices of one   */
+/* parity share no edge, so the order among pairs does not matter.           */
+/* Spin i = m*S + q.  The walker's initial spin (2t+j, q) is +1 when the top */
+/* bit of output j*S + q of pair t's generator is set.                       */
+/* ------------------------------------------------------------------------ */
+static void metropolis_at(orc_chain *c, int32_t w, int32_t i, uint32_t u, double beta) {
+  int8_t *s = c->s + (size_t)w * c->N;
+  int32_t *he = c->heff + (size_t)w * c->N;
+  int32_t d = s[i] * he[i];
+  int accept;
+  if (d <= 0) {
+    accept = 1;
+  } else if (c->accept_kind == ORC_ACCEPT_EXACT) {
+    accept = (double)u * 0x1p-32 < exp(-2.0 * beta * (double)d);
+  } else {
+    accept = u <= orc_approx_threshold(beta, d, c->accept_kind);
+  }
+  if (accept) {
+    int32_t old2 = 2 * s[i];
+    for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] -= old2 * c->cj[e];
+    s[i] = (int8_t)-s[i];
+    c->E[w] += 2 * d;
+    c->flips[w]++;
+  }
+}
+
+static void sweep_walker_pairs(orc_chain *c, int32_t w) {
+  const int32_t S = c->pS, P = c->pM / 2;
+  const double beta = c->beta[c->temp_of[w]];
+  for (int32_t parity = 0; parity < 2; parity++)
+    for (int32_t t = 0; t < P; t++) {
+      orc_mt *g = &c->pmt[(size_t)w * P + t];
+      const int32_t m = 2 * t + parity;
+      for (int32_t q = 0; q < S; q++) metropolis_at(c, w, m * S + q, orc_mt_next(g), beta);
+    }
+}
+
+int32_t orc_set_pairs(orc_chain *c, int32_t S, int32_t M, const uint32_t *pair_seed) {
+  if (!pair_seed || S < 1 || M < 2 || (M & 1) || (int64_t)S * M != c->N || c->two_field) return -1;
+  const int32_t P = M / 2;
+  free(c->pmt);
+  c->pmt = (orc_mt *)malloc(sizeof(orc_mt) * (size_t)c->K * P);
+  c->pairs = 1;
+  c->pS = S;
+  c->pM = M;
+  for (int32_t w = 0; w < c->K; w++) {
+    int8_t *s = c->s + (size_t)w * c->N;
+    for (int32_t t = 0; t < P; t++) {
+      orc_mt *g = &c->pmt[(size_t)w * P + t];
+      orc_mt_seed(g, pair_seed[(size_t)w * P + t]);
+      for (int32_t j = 0; j < 2; j++)
+        for (int32_t q = 0; q < S; q++) s[(2 * t + j) * S + q] = (orc_mt_next(g) >> 31) ? 1 : -1;
+    }
+    recompute(c, w);
+  }
+  return 0;
+}
+
+void orc_get_pair_mt(const orc_chain *c, uint32_t *win, int64_t *used) {
+  const int32_t n = c->pairs ? c->K * (c->pM / 2) : 0;
+  for (int32_t i = 0; i < n; i++) {
+    orc_mt_window(&c->pmt[i], win + (size_t)i * 624);
+    used[i] = c->pmt[i].n;
+  }
+}
+
 /* Fig. 1: for each spin in order, draw a uniform; flip if it is below the
  * flip probability; after a flip update the local fields of the neighbours. */
 static void sweep_walker(orc_chain *c, int32_t w) {
   if (c->two_field) {
     sweep_walker_two_field(c, w);
+    return;
+  }
+  if (c->pairs) {
+    sweep_walker_pairs(c, w);
     return;
   }
   const int32_t N = c->N;

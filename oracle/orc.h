@@ -97,6 +97,14 @@ int64_t orc_bond_of(const orc_chain *c, int32_t w);
 void orc_get_bond(const orc_chain *c, int64_t *out);        /* [K] running B */
 void orc_get_tau_fields(const orc_chain *c, int32_t *out);  /* [K][N] */
 
+/* Layer-pair order (Sec. 3.2, Fig. 12c): for a layered system of M (even)
+ * slices of S spins (spin m*S + q), walker w's pair t = slices (2t, 2t+1)
+ * draws from its own generator, seeded pair_seed[w*(M/2) + t]; a sweep visits
+ * the even slices, then the odd ones, each in index order.  Redraws the
+ * initial spins from the pair generators.  Returns 0, or -1 on bad input. */
+int32_t orc_set_pairs(orc_chain *c, int32_t S, int32_t M, const uint32_t *pair_seed);
+void orc_get_pair_mt(const orc_chain *c, uint32_t *win /*[K*M/2][624]*/, int64_t *used);
+
 #ifdef __cplusplus
 }
 #endif

@@ -365,21 +365,24 @@ static void sweep_walker_two_field(orc_chain *c, int32_t w) {
 /* Spin i = m*S + q.  The walker's initial spin (2t+j, q) is +1 when the top */
 /* bit of output j*S + q of pair t's generator is set.                       */
 /* ------------------------------------------------------------------------ */
+/* One Metropolis step of spin i of walker w with uniform word u (Fig. 1). */
 static void metropolis_at(orc_chain *c, int32_t w, int32_t i, uint32_t u, double beta) {
   int8_t *s = c->s + (size_t)w * c->N;
   int32_t *he = c->heff + (size_t)w * c->N;
-  int32_t d = s[i] * he[i];
+  int32_t d = s[i] * he[i];    /* flipping changes the cost by 2d */
   int accept;
   if (d <= 0) {
-    accept = 1;
+    accept = 1; /* probability min(1, exp(-beta*2d)) = 1 */
   } else if (c->accept_kind == ORC_ACCEPT_EXACT) {
-    accept = (double)u * 0x1p-32 < exp(-2.0 * beta * (double)d);
+    double p = exp(-2.0 * beta * (double)d);
+    double uniform = (double)u * 0x1p-32; /* in [0, 1) */
+    accept = uniform < p;
   } else {
     accept = u <= orc_approx_threshold(beta, d, c->accept_kind);
   }
   if (accept) {
-    int32_t old2 = 2 * s[i];
-    for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] -= old2 * c->cj[e];
+    int32_t two_s = 2 * s[i]; /* the old spin value */
+    for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] -= two_s * c->cj[e];
     s[i] = (int8_t)-s[i];
     c->E[w] += 2 * d;
     c->flips[w]++;
@@ -438,30 +441,11 @@ static void sweep_walker(orc_chain *c, int32_t w) {
     return;
   }
   const int32_t N = c->N;
-  int8_t *s = c->s + (size_t)w * N;
-  int32_t *he = c->heff + (size_t)w * N;
   const double beta = c->beta[c->temp_of[w]];
   orc_mt *g = &c->mt[w];
   for (int32_t i = 0; i < N; i++) {
     uint32_t u = orc_mt_next(g); /* one draw per spin, also when dE <= 0 */
-    int32_t d = s[i] * he[i];    /* flipping changes the cost by 2d */
-    int accept;
-    if (d <= 0) {
-      accept = 1; /* probability min(1, exp(-beta*2d)) = 1 */
-    } else if (c->accept_kind == ORC_ACCEPT_EXACT) {
-      double p = exp(-2.0 * beta * (double)d);
-      double uniform = (double)u * 0x1p-32; /* in [0, 1) */
-      accept = uniform < p;
-    } else {
-      accept = u <= orc_approx_threshold(beta, d, c->accept_kind);
-    }
-    if (accept) {
-      int32_t two_s = 2 * s[i]; /* the old spin value */
-      for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] -= two_s * c->cj[e];
-      s[i] = (int8_t)-s[i];
-      c->E[w] += 2 * d;
-      c->flips[w]++;
-    }
+    metropolis_at(c, w, i, u, beta);
   }
 }
 

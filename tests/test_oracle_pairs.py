@@ -17,7 +17,8 @@ def test_pair_pin(pin):
     pin()
 
 
-# (name, original text, planted mistake)
+# (name, original text, planted mistake); the single-site step is shared with the
+# canonical sweep and audited with it (test_oracle_mutations.py)
 MUTATIONS = [
     ("odd_slices_first", "const int32_t m = 2 * t + parity;", "const int32_t m = 2 * t + 1 - parity;"),
     ("reverse_in_slice_order", "for (int32_t q = 0; q < S; q++) metropolis_at(c, w, m * S + q, orc_mt_next(g), beta);",
@@ -27,10 +28,6 @@ MUTATIONS = [
     ("init_slices_swapped", "s[(2 * t + j) * S + q] = (orc_mt_next(g) >> 31)", "s[(2 * t + 1 - j) * S + q] = (orc_mt_next(g) >> 31)"),
     ("beta_of_walker", "const double beta = c->beta[c->temp_of[w]];\n  for (int32_t parity",
      "const double beta = c->beta[w];\n  for (int32_t parity"),
-    ("pair_field_sign", "for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] -= old2 * c->cj[e];",
-     "for (int32_t e = c->rp[i]; e < c->rp[i + 1]; e++) he[c->ci[e]] += old2 * c->cj[e];"),
-    ("pair_energy_step", "    c->E[w] += 2 * d;\n    c->flips[w]++;\n  }\n}\n\nstatic void sweep_walker_pairs",
-     "    c->E[w] += d;\n    c->flips[w]++;\n  }\n}\n\nstatic void sweep_walker_pairs"),
 ]
 
 RUNNER = r"""

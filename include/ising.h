@@ -265,6 +265,42 @@ int32_t ising_two_field_row(double a, double c, int32_t ds, int32_t dt, int32_t 
  * carry the transfer factor exp(c s s').                                     */
 int32_t ising_trotter_weights(const double *beta, int32_t n, int32_t M, double gamma, double *a, double *c);
 
+/* ---- layer-pair order (the paper's GPU layout) ------------------------------
+ * Section 3.2, Figure 12c: the slices of a model are grouped in pairs
+ * (2t, 2t+1) that are interlaced over GPU threads; each thread has its own
+ * random number generator and first attempts the spins of its even slice,
+ * then, after all threads are done, those of its odd slice.  This is a
+ * different chain from the sequential sweep above, built as its own mode:
+ *   - walker r has M/2 MT19937 generators, lane (pl0(r) + t) for pair t, where
+ *     lanes are numbered walker by walker in load order (system s, walker j of
+ *     it: lanes sum_{s'<s} K_s' M_s'/2 + j M_s/2 + t); generator lane l is
+ *     seeded with init_genrand(pair_seeds[l]);
+ *   - initial spin (2t + j, q) is +1 iff the top bit of output j S + q of
+ *     generator t is set;
+ *   - a sweep visits every even slice, spins in ascending q, one output of the
+ *     slice's pair generator per spin, then every odd slice the same way
+ *     (slices of one parity share no edge, so they run side by side); the flip
+ *     test, thresholds, acceptance variants, energies and swap rounds are those
+ *     of the one-field form above;
+ *   - after n outputs, word x_{n+i} (i < 624) of a generator is at row
+ *     (n + i) mod 624 of its column: pair_mt is [624][lanes] (device, caller
+ *     owned, ising_pairs_words elements).
+ * Needs every system to have an even number of slices, K * M/2 <= 1024 and
+ * its walkers' spins in LDS (ISING_E_RANGE otherwise), and the two-field form
+ * off.  One workgroup sweeps a whole system and runs its swap rounds, so one
+ * launch (per template class) covers any number of sweeps.  The state's walker
+ * streams (st->mt) are not used.                                              */
+int32_t ising_pairs_words(const ising_graph *g, int64_t *words);
+/* Seed the pair generators (host pair_seeds[lanes]) and swap streams (host
+ * swap_seeds[n_sys]), draw the initial spins, compute energies, put walker j
+ * of each system at slot j, clear the counters.                              */
+int32_t ising_pairs_init(const ising_graph *g, ising_state *st, uint32_t *pair_mt, const uint32_t *pair_seeds,
+                         const uint32_t *swap_seeds, void *stream);
+/* n_sweeps layer-pair sweeps of every walker, with a swap round after each
+ * sweep whose running count is a multiple of swap_every (> 0; 0 = never).   */
+int32_t ising_pairs_sweep(const ising_graph *g, ising_state *st, uint32_t *pair_mt, int32_t n_sweeps,
+                          int32_t swap_every, void *stream);
+
 /* ---- learned cell proposal --------------------------------------------------
  * An extension of the method (the paper has no learned part): a unit cell of
  * 8 spins of one slice is re-proposed jointly by a 17 -> 128 -> 128 -> 8 ReLU

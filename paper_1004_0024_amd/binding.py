@@ -89,6 +89,9 @@ def lib():
             "ising_set_two_field": ([P, P, P, P], i32),
             "ising_two_field_row": ([C.c_double, C.c_double, i32, i32, i32, P], i32),
             "ising_trotter_weights": ([P, i32, i32, C.c_double, P, P], i32),
+            "ising_pairs_words": ([P, P], i32),
+            "ising_pairs_init": ([P, P, P, P, P, P], i32),
+            "ising_pairs_sweep": ([P, P, P, i32, i32, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -321,6 +324,39 @@ class State:
         """One pass of exact heat-bath cell moves (all colour classes)."""
         _check(lib().ising_heatbath_cells(self.graph.handle, C.byref(self._s), C.c_uint64(key), int(pass_index),
                                           C.c_void_p(moves.data_ptr()) if moves is not None else None, _stream()))
+
+    # ---- layer-pair order (the paper's GPU layout, Sec. 3.2) ----
+    def pairs_init(self, pair_seeds, swap_seeds):
+        """Start the layer-pair chain: generator lanes seeded from pair_seeds (one per
+        pair of slices of every walker, walker-major), swap streams from swap_seeds."""
+        import torch
+        words = C.c_int64(0)
+        _check(lib().ising_pairs_words(self.graph.handle, C.byref(words)))
+        self.pair_lanes = int(words.value) // 624
+        self.t["pair_mt"] = torch.zeros(max(int(words.value), 1), dtype=torch.int32, device=self.graph.tables.device)
+        ps = np.ascontiguousarray(pair_seeds, np.uint32)
+        ss = np.ascontiguousarray(swap_seeds, np.uint32)
+        assert ps.shape == (self.pair_lanes,) and ss.shape == (self.graph.n_sys,)
+        _check(lib().ising_pairs_init(self.graph.handle, C.byref(self._s), C.c_void_p(self.t["pair_mt"].data_ptr()),
+                                      _np_ptr(ps), _np_ptr(ss), _stream()))
+        return self
+
+    def pairs_sweep(self, n_sweeps, swap_every=1):
+        _check(lib().ising_pairs_sweep(self.graph.handle, C.byref(self._s), C.c_void_p(self.t["pair_mt"].data_ptr()),
+                                       int(n_sweeps), int(swap_every), _stream()))
+
+    def pair_windows(self, system):
+        """[lanes of `system`][624] words of its generator lanes, oldest first (each lane
+        of the system has delivered 2 S (1 + sweeps) outputs)."""
+        l0 = 0
+        for sysm in self.graph.systems[:system]:
+            l0 += len(sysm.beta) * (int(sysm.M) // 2)
+        sysm = self.graph.systems[system]
+        lanes = len(sysm.beta) * (int(sysm.M) // 2)
+        cols = self.t["pair_mt"][: 624 * self.pair_lanes].view(624, self.pair_lanes)[:, l0:l0 + lanes]
+        a = cols.cpu().numpy().view(np.uint32)
+        n = 2 * int(sysm.S) * (1 + self.sweeps)
+        return np.ascontiguousarray(a[(n + np.arange(624)) % 624].T)
 
     def refresh_energies(self):
         """Recompute the running cost and tau-bond sum of every walker from its spins."""

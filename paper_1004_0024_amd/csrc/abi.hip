@@ -376,6 +376,12 @@ struct ising_graph {
   // two-field form: graph-wide bounds of d_sp and d_t, row words (0: rows too long)
   int32_t qds = 0, qdt = 0, qrow = 0;
   bool two_field = false;
+  // layer-pair order: generator lanes, launch size, classes present ("" if supported)
+  int64_t pair_lanes = 0;
+  int32_t pair_threads = 0;
+  size_t pair_lds = 0;
+  uint32_t pair_classes = 0;
+  std::string pair_why;
   std::vector<double> qa, qc;  // per slot, while the two-field form is on
   // LDS words of a walker slot for system s in the current form
   int32_t walker_words(int32_t s) const {
@@ -522,6 +528,24 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     for (int p = 0; p < 5; ++p) si.pc[p] = h.pc[p];
     si.rows = 0;
     for (int p = 0; p < h.n_phases; ++p) si.rows = std::max(si.rows, h.pc[p + 1] - h.pc[p]);
+    // layer-pair order: one generator lane per pair of slices of every walker
+    si.pl0 = (int32_t)std::min<int64_t>(g.pair_lanes, INT32_MAX);
+    {
+      const int64_t lanes = (int64_t)h.K * (h.M / 2);
+      const size_t lds = ((size_t)h.K * pair_walker_words(si.WW) + kLadderWords) * 4;
+      if (g.pair_why.empty()) {
+        if (h.M < 2 || h.M % 2)
+          g.pair_why = "system " + std::to_string(s) + " has an odd number of slices";
+        else if (lanes > 1024)
+          g.pair_why = "system " + std::to_string(s) + " needs more than 1024 lanes (K * M/2)";
+        else if (lds > 160 * 1024)
+          g.pair_why = "system " + std::to_string(s) + " needs more than 160 KiB of LDS";
+      }
+      g.pair_lanes += lanes;
+      g.pair_threads = std::max<int32_t>(g.pair_threads, (int32_t)((lanes + 63) / 64 * 64));
+      g.pair_lds = std::max(g.pair_lds, lds);
+      g.pair_classes |= 1u << (2 * h.cell + h.ring);
+    }
     si.row0 = g.cell_rows;  // a multiple of 64: a 64-row tile of cell moves lies in one system
     si.cell0 = g.total_cells;
     g.cell_rows += ((int64_t)si.rows * h.K + 63) / 64 * 64;
@@ -538,6 +562,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     for (int32_t k = 0; k < h.K; ++k) g.walker_sys.push_back((int32_t)s);
   }
   if (walker > INT32_MAX || slot > INT32_MAX) return fail(ISING_E_RANGE, "too many walkers");
+  if (g.pair_why.empty() && g.pair_lanes > INT32_MAX) g.pair_why = "too many generator lanes";
   for (const SysHost &h : hs) {
     g.qds = std::max(g.qds, h.ds);
     g.qdt = std::max(g.qdt, h.dt);
@@ -1185,6 +1210,76 @@ extern "C" int32_t ising_refresh_energies(const ising_graph *g, ising_state *st,
   if (rc) return rc;
   HIP_TRY(launch_observables(g->dev, dev_state(st), (int32_t)g->R, nullptr, 1, (hipStream_t)stream),
           "observables kernel");
+  return ISING_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Layer-pair order (Section 3.2, Figure 12c)
+// ---------------------------------------------------------------------------
+static int32_t check_pairs(const ising_graph *g) {
+  if (!g) return fail(ISING_E_INVAL, "layer-pair order: NULL graph");
+  if (!g->pair_why.empty()) return fail(ISING_E_RANGE, "layer-pair order: %s", g->pair_why.c_str());
+  if (g->two_field) return fail(ISING_E_STATE, "layer-pair order: the two-field form is on");
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_pairs_words(const ising_graph *g, int64_t *words) {
+  int32_t rc = check_pairs(g);
+  if (rc) return rc;
+  if (!words) return fail(ISING_E_INVAL, "pairs_words: NULL argument");
+  *words = (int64_t)kMtN * g->pair_lanes;
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_pairs_init(const ising_graph *g, ising_state *st, uint32_t *pair_mt,
+                                    const uint32_t *pair_seeds, const uint32_t *swap_seeds, void *stream) {
+  int32_t rc = check_pairs(g);
+  if (rc) return rc;
+  rc = check_state(st);
+  if (rc) return rc;
+  if (!pair_mt || !pair_seeds || !swap_seeds) return fail(ISING_E_INVAL, "pairs_init: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  DevState d = dev_state(st);
+  // seeds go to row 0; the seed kernel expands each lane's column
+  HIP_TRY(hipMemcpyAsync(pair_mt, pair_seeds, sizeof(uint32_t) * g->pair_lanes, hipMemcpyHostToDevice, s),
+          "pairs_init seeds");
+  HIP_TRY(hipMemcpy2DAsync(st->swap_mt, kMtN * sizeof(uint32_t), swap_seeds, sizeof(uint32_t), sizeof(uint32_t),
+                           (size_t)g->n_sys, hipMemcpyHostToDevice, s),
+          "pairs_init swap seeds");
+  HIP_TRY(hipStreamSynchronize(s), "pairs_init sync");
+  HIP_TRY(launch_pair_seed(pair_mt, g->pair_lanes, s), "pair seed kernel");
+  HIP_TRY(launch_seed(d, 0, g->n_sys, s), "swap seed kernel");
+  HIP_TRY(hipMemsetAsync(st->flips, 0, sizeof(uint64_t) * g->R, s), "pairs_init clear");
+  HIP_TRY(hipMemsetAsync(st->swap_att, 0, sizeof(uint64_t) * g->slots, s), "pairs_init clear");
+  HIP_TRY(hipMemsetAsync(st->swap_acc, 0, sizeof(uint64_t) * g->slots, s), "pairs_init clear");
+  HIP_TRY(hipMemsetAsync(st->stats, 0, sizeof(uint64_t) * ISING_N_STATS, s), "pairs_init clear");
+  HIP_TRY(hipMemsetAsync(st->wsteps, 0, sizeof(uint64_t) * 2 * g->R, s), "pairs_init clear");
+  HIP_TRY(launch_labels(g->dev, d, (int32_t)g->R, g->n_sys, s), "labels kernel");
+  HIP_TRY(launch_pairs(g->dev, d, pair_mt, g->pair_lanes, g->n_sys, g->pair_threads, g->pair_lds, g->pair_classes,
+                       0, 1, LadderArgs{0, 0, 0, 0}, s),
+          "initial spins");
+  HIP_TRY(launch_observables(g->dev, d, (int32_t)g->R, nullptr, 1, s), "initial energies");
+  st->sweeps = 0;
+  st->rounds = 0;
+  return ISING_OK;
+}
+
+extern "C" int32_t ising_pairs_sweep(const ising_graph *g, ising_state *st, uint32_t *pair_mt, int32_t n_sweeps,
+                                     int32_t swap_every, void *stream) {
+  int32_t rc = check_pairs(g);
+  if (rc) return rc;
+  rc = check_state(st);
+  if (rc) return rc;
+  if (!pair_mt) return fail(ISING_E_INVAL, "pairs_sweep: NULL generator array");
+  if (n_sweeps < 0 || swap_every < 0) return fail(ISING_E_INVAL, "pairs_sweep: negative count");
+  if (st->sweeps < 0) return fail(ISING_E_STATE, "pairs_sweep: state not initialised");
+  if (n_sweeps == 0) return ISING_OK;
+  const LadderArgs la{swap_every, 0, st->sweeps, st->rounds};
+  HIP_TRY(launch_pairs(g->dev, dev_state(st), pair_mt, g->pair_lanes, g->n_sys, g->pair_threads, g->pair_lds,
+                       g->pair_classes, n_sweeps, 0, la, (hipStream_t)stream),
+          "layer-pair sweep kernel");
+  if (swap_every > 0) st->rounds += (st->sweeps + n_sweeps) / swap_every - st->sweeps / swap_every;
+  st->sweeps += n_sweeps;
   return ISING_OK;
 }
 

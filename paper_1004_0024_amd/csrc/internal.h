@@ -31,7 +31,7 @@ struct SysInfo {
   int32_t cl0;             // first entry of this system's cell list
   int32_t pc[5];           // phase p owns cell-list entries [pc[p], pc[p+1])
   int32_t rows;            // proposal work rows per walker (largest phase)
-  int32_t pad2;
+  int32_t pl0;             // layer-pair order: first generator lane of walker 0 (M/2 per walker)
   int64_t row0;            // first proposal work row of walker 0
   int64_t cell0;           // global index of walker 0's cell 0 (cells numbered walker-major)
 };
@@ -164,5 +164,20 @@ hipError_t launch_collect_cells(const DevTables &t, const DevState &s, int32_t n
 hipError_t launch_reduce_stats(const DevState &s, int32_t R, int32_t slots, hipStream_t st);
 hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32_t n_sys,
                          hipStream_t st);
+// Layer-pair order: expand the seeds in row 0 of every generator lane
+// (pair_mt is [kMtN][n_lanes]), and `n_sweeps` sweeps (init_mode: draw the
+// initial spins) over every system, one workgroup per system, one launch per
+// (cell, ring) class present (bit 2 cell + ring of `classes`).
+hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st);
+hipError_t launch_pairs(const DevTables &t, const DevState &s, uint32_t *pair_mt, int64_t n_lanes, int32_t n_sys,
+                        int32_t threads, size_t lds, uint32_t classes, int32_t n_sweeps, int32_t init_mode,
+                        LadderArgs la, hipStream_t st);
+// LDS words of one walker in the layer-pair kernel: M rows of RS spin words,
+// threshold row, reduction words; odd, so the walkers of a wavefront use
+// different banks.
+__host__ __device__ inline int32_t pair_walker_words(int32_t WW) {
+  const int32_t w = WW + kThrRow + 4;
+  return w | 1;
+}
 
 }  // namespace ising

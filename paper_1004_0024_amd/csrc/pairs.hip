@@ -1,0 +1,265 @@
+// Layer-pair order: the paper's GPU layout (Section 3.2, Figure 12c) as a
+// chain of its own.  The M slices of a walker form M/2 pairs (2t, 2t+1); lane
+// t of the walker owns pair t and its MT19937 generator.  A sweep visits every
+// even slice (lane t its slice 2t, spins in index order, one draw of its
+// generator per spin), then every odd slice.  Slices of one parity share no
+// edge, so the lanes of a phase run side by side.  The paper pushes field
+// updates to the slice on one side during a phase and to the other side after
+// it, so that no two threads write one field at once; here a spin's field is
+// pulled from its neighbours' bits when it is visited, which needs neither.
+//
+// One workgroup holds a whole system (K walkers x M/2 lanes), so swap rounds
+// run in the kernel between sweeps.  LDS per walker: the spins (M rows of RS
+// words), its slot's threshold row and reduction words.  A lane keeps the
+// word of 32 spins it is sweeping in a register, with the words of the slices
+// above and below.  The generators are interlaced in HBM ([624][lanes]: word
+// slot r of every generator in one row, so a wavefront's accesses are
+// coalesced) and updated in place 16 outputs at a time: per output one read of
+// slots n and n + 397 and one write, the 12 bytes per attempt of the HBM
+// roofline model.
+#include "internal.h"
+#include "mt19937.h"
+#include "swap_round.h"
+
+namespace ising {
+
+// ---- seeding: row 0 of each lane holds the seed ---------------------------
+__global__ void pair_seed_kernel(uint32_t *pmt, int64_t n_lanes) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_lanes) return;
+  uint32_t v = pmt[l];
+  for (int i = 1; i < kMtN; ++i) {
+    v = mt_seed_step(v, (uint32_t)i);
+    pmt[(int64_t)i * n_lanes + l] = v;
+  }
+}
+
+hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st) {
+  if (n_lanes > 0)
+    hipLaunchKernelGGL(pair_seed_kernel, dim3((unsigned)((n_lanes + 255) / 256)), dim3(256), 0, st, pair_mt,
+                       n_lanes);
+  return hipGetLastError();
+}
+
+constexpr int kPairBatch = 16;  // generator outputs per batch
+
+// The next nb (<= kPairBatch) outputs of a lane's generator, in place: slot k
+// holds x_{n-624} before and x_n after; output i reads slots pos+i, pos+i+1
+// and pos+i+397 (mod 624), none of them written earlier in the batch.
+__device__ __forceinline__ void gen_batch(uint32_t *gen, int64_t n_lanes, int pos, int nb, uint32_t *u) {
+  uint32_t a[kPairBatch + 1], m[kPairBatch];
+#pragma unroll
+  for (int i = 0; i <= kPairBatch; ++i)
+    if (i <= nb) {
+      int k = pos + i;
+      if (k >= kMtN) k -= kMtN;
+      a[i] = gen[(int64_t)k * n_lanes];
+    }
+#pragma unroll
+  for (int i = 0; i < kPairBatch; ++i)
+    if (i < nb) {
+      int k = pos + i + kMtM;
+      if (k >= kMtN) k -= kMtN;
+      if (k >= kMtN) k -= kMtN;
+      m[i] = gen[(int64_t)k * n_lanes];
+    }
+#pragma unroll
+  for (int i = 0; i < kPairBatch; ++i)
+    if (i < nb) {
+      int k = pos + i;
+      if (k >= kMtN) k -= kMtN;
+      const uint32_t x = mt_next_word(a[i], a[i + 1], m[i]);
+      gen[(int64_t)k * n_lanes] = x;
+      u[i] = mt_temper(x);
+    }
+}
+
+template <bool CELL, bool RING>
+__global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, uint32_t *pmt, int64_t n_lanes,
+                                                     int32_t n_sweeps, int32_t init_mode, LadderArgs la) {
+  extern __shared__ uint32_t lds[];
+  const SysInfo sy = T.sys[blockIdx.x];
+  if ((sy.cell != 0) != CELL || (sy.ring != 0) != RING) return;  // the launch of its class takes it
+  const int S = sy.S, M = sy.M, RS = sy.RS, WW = sy.WW, K = sy.K, P = M >> 1;
+  const int PW = pair_walker_words(WW);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int w = tid / P, t = tid - w * P;
+  const bool live = w < K;
+  uint32_t *slot = lds + (live ? w : 0) * PW;
+  const uint32_t *thw = slot + WW;
+  int32_t *acc = (int32_t *)(slot + WW + kThrRow);
+
+  // ---- load the walkers' spins, threshold rows and running costs ----
+  for (int i = tid; i < K * WW; i += nthr) {
+    const int ww = i / WW, j = i - ww * WW;
+    lds[ww * PW + j] = init_mode ? 0u : St.spins[sy.spin_word0 + (int64_t)ww * WW + j];
+  }
+  if (!init_mode)
+    for (int i = tid; i < K * kThrRow; i += nthr) {
+      const int ww = i / kThrRow, j = i - ww * kThrRow;
+      const int sl = St.temp_of[sy.walker0 + ww];
+      lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + sl) * kThrRow + j];
+    }
+  for (int i = tid; i < K * 4; i += nthr)
+    lds[(i >> 2) * PW + WW + kThrRow + (i & 3)] =
+        ((i & 3) == 0 && !init_mode) ? (uint32_t)St.energy[sy.walker0 + (i >> 2)] : 0u;
+  const bool ladder = la.swap_every > 0 && !init_mode;
+  uint32_t *swin = lds + K * PW;
+  int32_t *wat = (int32_t *)(swin + kMtN), *tof = wat + 256, *misc = tof + 256;
+  if (ladder) {
+    for (int j = tid; j < kMtN; j += nthr) swin[j] = St.swap_mt[(size_t)blockIdx.x * kMtN + j];
+    for (int k = tid; k < K; k += nthr) {
+      wat[k] = St.walker_at[sy.slot0 + k];
+      tof[k] = St.temp_of[sy.walker0 + k];
+    }
+    if (tid == 0) misc[0] = misc[1] = 0;
+  }
+  __syncthreads();
+
+  // ---- this lane's generator and slices ----
+  uint32_t *gen = pmt + (live ? (int64_t)sy.pl0 + tid : 0);
+  int pos = init_mode ? 0 : (int)((2 * (int64_t)S * (1 + la.sweeps0)) % kMtN);
+  const TmplSpin *tm = T.tmpl + sy.tmpl0;
+  int dE = 0, nfl = 0;  // sum of d over flips (the cost changes by 2d), flips
+  int64_t n_rounds = 0;
+  const int nsw = init_mode ? 1 : n_sweeps;
+  for (int sw = 0; sw < nsw; ++sw) {
+    for (int par = 0; par < 2; ++par) {
+      if (live) {
+        const int row = 2 * t + par;
+        int ru = row - 1, rd = row + 1;
+        if (ru < 0) ru = RING ? M - 1 : -1;
+        if (rd >= M) rd = RING ? 0 : -1;
+        uint32_t *rp = slot + row * RS;
+        const uint32_t *up = slot + (ru < 0 ? row : ru) * RS;
+        const uint32_t *dn = slot + (rd < 0 ? row : rd) * RS;
+        const uint32_t umask = ru < 0 ? 0u : ~0u, dmask = rd < 0 ? 0u : ~0u;
+        const int ntau = (ru >= 0 ? 1 : 0) + (rd >= 0 ? 1 : 0);
+        for (int wq = 0; wq * 32 < S; ++wq) {
+          const int nq = min(32, S - wq * 32);
+          uint32_t cur = rp[wq];
+          const uint32_t tu = up[wq] & umask, td = dn[wq] & dmask;
+          for (int n0 = 0; n0 < nq; n0 += kPairBatch) {
+            const int nb = min(kPairBatch, nq - n0);
+            uint32_t u[kPairBatch];
+            gen_batch(gen, n_lanes, pos, nb, u);
+            pos += nb;
+            if (pos >= kMtN) pos -= kMtN;
+#pragma unroll
+            for (int i = 0; i < kPairBatch; ++i) {
+              if (i >= nb) break;
+              const int b = n0 + i;  // bit of the spin in the word
+              if (init_mode) {     // initial spin: the top bit of the output
+                cur |= (u[i] >> 31) << b;
+                continue;
+              }
+              const TmplSpin &ts = tm[wq * 32 + b];
+              // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms
+              int hs = ts.h;
+              if (CELL) {  // the other half of the spin's K4,4 cell: a nibble of this word
+                const uint32_t nib = (cur >> ((b & ~3) ^ 4)) & 15u;
+                const uint32_t spread = __umul24(nib, 0x00204081u) & 0x01010101u;
+                hs = __builtin_amdgcn_sdot4((int)spread, ts.jpack, hs, false);
+                hs -= ts.J[0] + ts.J[1] + ts.J[2] + ts.J[3];
+              }
+#pragma unroll
+              for (int j = CELL ? 4 : 0; j < kMaxDeg; ++j) {
+                if (j >= ts.deg) break;
+                const int qq = ts.nbr[j];
+                const int woff = (qq >> 5) - wq;
+                const uint32_t nw = woff == 0 ? cur : rp[wq + woff];
+                hs += (2 * (int)((nw >> (qq & 31)) & 1u) - 1) * ts.J[j];
+              }
+              const int jt = ts.Jtau;
+              hs += 2 * jt * (int)(((tu >> b) & 1u) + ((td >> b) & 1u)) - jt * ntau;
+              const int dn_ = -(int)((~cur >> b) & 1u);  // -1 for a spin down, 0 for up
+              const int d = (hs ^ dn_) - dn_;            // s * h_eff
+              if (u[i] <= thw[d > 0 ? d : 0]) {
+                cur ^= 1u << b;
+                dE += d;
+                ++nfl;
+              }
+            }
+          }
+          rp[wq] = cur;
+        }
+      }
+      __syncthreads();  // this parity's slices are final before the other parity reads them
+    }
+    if (ladder && (la.sweeps0 + sw + 1) % la.swap_every == 0) {
+      if (live && dE) atomicAdd(&acc[0], 2 * dE);
+      dE = 0;
+      __syncthreads();
+      if (tid == 0)
+        ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
+                          WW + kThrRow);
+      ++n_rounds;
+      __syncthreads();
+      for (int i = tid; i < K * kThrRow; i += nthr) {
+        const int ww = i / kThrRow, j = i - ww * kThrRow;
+        lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + tof[ww]) * kThrRow + j];
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- write back ----
+  if (live && !init_mode) {
+    if (dE) atomicAdd(&acc[0], 2 * dE);
+    if (nfl) atomicAdd(&acc[1], nfl);
+  }
+  __syncthreads();
+  for (int i = tid; i < K * WW; i += nthr) {
+    const int ww = i / WW, j = i - ww * WW;
+    St.spins[sy.spin_word0 + (int64_t)ww * WW + j] = lds[ww * PW + j];
+  }
+  if (!init_mode && tid < K) {
+    const int r = sy.walker0 + tid;
+    const int32_t *a = (const int32_t *)(lds + tid * PW + WW + kThrRow);
+    St.energy[r] = a[0];
+    St.flips[r] += (unsigned long long)(uint32_t)a[1];
+  }
+  if (ladder) {
+    const int h = misc[0];
+    for (int j = tid; j < kMtN; j += nthr) St.swap_mt[(size_t)blockIdx.x * kMtN + j] = swin[(h + j) % kMtN];
+    for (int k = tid; k < K; k += nthr) {
+      St.walker_at[sy.slot0 + k] = wat[k];
+      St.temp_of[sy.walker0 + k] = tof[k];
+    }
+    if (tid == 0 && misc[1]) atomicAdd((unsigned long long *)&St.stats[0], (unsigned long long)misc[1]);
+  }
+}
+
+template <bool CELL, bool RING>
+static hipError_t launch_pairs_variant(const DevTables &t, const DevState &s, uint32_t *pmt, int64_t n_lanes,
+                                       int32_t n_sys, int32_t threads, size_t lds, int32_t n_sweeps,
+                                       int32_t init_mode, LadderArgs la, hipStream_t st) {
+  auto kern = pairs_kernel<CELL, RING>;
+  static bool lds_limit_set = false;
+  if (!lds_limit_set && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_limit_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(n_sys), dim3(threads), lds, st, t, s, pmt, n_lanes, n_sweeps, init_mode, la);
+  return hipGetLastError();
+}
+
+// classes: bit (2 cell + ring) set when some system is of that class; one
+// launch per class present (systems of other classes return at once).
+hipError_t launch_pairs(const DevTables &t, const DevState &s, uint32_t *pair_mt, int64_t n_lanes, int32_t n_sys,
+                        int32_t threads, size_t lds, uint32_t classes, int32_t n_sweeps, int32_t init_mode,
+                        LadderArgs la, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess && (classes & 8u))
+    e = launch_pairs_variant<true, true>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+  if (e == hipSuccess && (classes & 4u))
+    e = launch_pairs_variant<true, false>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+  if (e == hipSuccess && (classes & 2u))
+    e = launch_pairs_variant<false, true>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+  if (e == hipSuccess && (classes & 1u))
+    e = launch_pairs_variant<false, false>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+  return e;
+}
+
+}  // namespace ising

@@ -144,6 +144,44 @@ def two_field_leg(steps, gamma=1.0):
             "wave_steps_with_flip": stats["wave_flip_steps"] / max(1, stats["wave_steps"])}
 
 
+def pairs_leg(name, n_sweeps, reps):
+    """The layer-pair order (the paper's GPU layout, Sec. 3.2, Fig. 12c) on a workload:
+    one launch runs `n_sweeps` sweeps of every walker with a swap round after each
+    (whole systems per workgroup); `reps` launches timed with HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1004_0024_amd as pa
+    from gen import make_workload
+
+    wl = make_workload(name)
+    g = pa.Graph(wl.systems)
+    st = pa.State(g)
+    lanes = sum(s.K * (s.M // 2) for s in wl.systems)
+    st.pairs_init((100_000 + np.arange(lanes)).astype(np.uint32), wl.swap_seeds)
+    st.pairs_sweep(n_sweeps, 1)  # warm-up
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    torch.cuda.synchronize()
+    for k in range(reps):
+        evs[2 * k].record(stream)
+        st.pairs_sweep(n_sweeps, 1)
+        evs[2 * k + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = [evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(reps)]
+    avg = sum(ms) / reps
+    attempts = g.attempts_per_sweep * n_sweeps
+    achieved = BYTES_PER_ATTEMPT * attempts / (avg / 1e3) / 1e9
+    stats = st.stats()
+    return {"workload": wl.name + ", layer-pair order", "sweeps_per_launch": n_sweeps, "launches": reps,
+            "kernel_ms": {"mean": avg, "min": min(ms), "max": max(ms)}, "us_per_sweep": avg * 1e3 / n_sweeps,
+            "value": attempts / (avg / 1e3), "unit": "spin-flip attempts/s",
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT,
+                         "kernel": "pairs_kernel"},
+            "flip_rate": stats["flips"] / max(1, g.attempts_per_sweep * st.sweeps)}
+
+
 def learned_leg(ess_steps, train_rows=1 << 20):
     """Learned cell proposal on the 256 x 32-walker, 4,096-spin workload: train the
     network on the GPU from plain-chain samples, then effective samples per second of
@@ -261,6 +299,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
     ap.add_argument("--no-batches", action="store_true", help="skip the many-replica and uneven-batch legs")
     ap.add_argument("--no-two-field", action="store_true", help="skip the two-field (QMC) leg")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the layer-pair order leg")
     ap.add_argument("--ess-steps", type=int, default=10000,
                     help="chain steps per ESS estimate in the learned-proposal leg")
     args = ap.parse_args()
@@ -373,6 +412,8 @@ def main():
     if not args.no_two_field:
         out["two_field"] = two_field_leg(max(2, args.steps // 2))
         out["two_field"]["over_one_field"] = out["two_field"]["value"] / value
+    if not args.no_pairs:
+        out["layer_pairs"] = [pairs_leg("B", 100, max(2, args.steps // 2)), pairs_leg("A", 1000, 3)]
     if not args.no_learned:
         out["effective_samples"] = learned_leg(args.ess_steps)
     if not args.no_cpu_baseline:

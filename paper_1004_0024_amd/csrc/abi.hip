@@ -532,10 +532,12 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
     si.pl0 = (int32_t)std::min<int64_t>(g.pair_lanes, INT32_MAX);
     {
       const int64_t lanes = (int64_t)h.K * (h.M / 2);
-      const size_t lds = ((size_t)h.K * pair_walker_words(si.WW) + kLadderWords) * 4;
+      const size_t lds = ((size_t)h.K * pair_walker_words(si.WW) + kLadderWords + 3 * (size_t)h.S) * 4;
       if (g.pair_why.empty()) {
         if (h.M < 2 || h.M % 2)
           g.pair_why = "system " + std::to_string(s) + " has an odd number of slices";
+        else if (!h.cell || h.deg > 6)
+          g.pair_why = "system " + std::to_string(s) + " is not a grid of K4,4 cells";
         else if (lanes > 1024)
           g.pair_why = "system " + std::to_string(s) + " needs more than 1024 lanes (K * M/2)";
         else if (lds > 160 * 1024)
@@ -544,7 +546,7 @@ static int32_t plan(const std::vector<SysHost> &hs, ising_graph &g) {
       g.pair_lanes += lanes;
       g.pair_threads = std::max<int32_t>(g.pair_threads, (int32_t)((lanes + 63) / 64 * 64));
       g.pair_lds = std::max(g.pair_lds, lds);
-      g.pair_classes |= 1u << (2 * h.cell + h.ring);
+      g.pair_classes |= 1u << h.ring;
     }
     si.row0 = g.cell_rows;  // a multiple of 64: a 64-row tile of cell moves lies in one system
     si.cell0 = g.total_cells;

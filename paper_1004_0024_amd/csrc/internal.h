@@ -167,7 +167,7 @@ hipError_t launch_labels(const DevTables &t, const DevState &s, int32_t R, int32
 // Layer-pair order: expand the seeds in row 0 of every generator lane
 // (pair_mt is [kMtN][n_lanes]), and `n_sweeps` sweeps (init_mode: draw the
 // initial spins) over every system, one workgroup per system, one launch per
-// (cell, ring) class present (bit 2 cell + ring of `classes`).
+// slice class present (bit 0: open slices, bit 1: a ring).
 hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st);
 hipError_t launch_pairs(const DevTables &t, const DevState &s, uint32_t *pair_mt, int64_t n_lanes, int32_t n_sys,
                         int32_t threads, size_t lds, uint32_t classes, int32_t n_sweeps, int32_t init_mode,

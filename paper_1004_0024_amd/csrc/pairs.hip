@@ -10,11 +10,13 @@
 //
 // One workgroup holds a whole system (K walkers x M/2 lanes), so swap rounds
 // run in the kernel between sweeps.  LDS per walker: the spins (M rows of RS
-// words), its slot's threshold row and reduction words.  A lane keeps the
+// words), its slot's threshold row and reduction words; per workgroup the swap
+// state and a three-word record per template spin (every lane visits the same
+// spin at the same time, so a record is one broadcast read).  A lane keeps the
 // word of 32 spins it is sweeping in a register, with the words of the slices
 // above and below.  The generators are interlaced in HBM ([624][lanes]: word
 // slot r of every generator in one row, so a wavefront's accesses are
-// coalesced) and updated in place 16 outputs at a time: per output one read of
+// coalesced) and updated in place 8 outputs at a time: per output one read of
 // slots n and n + 397 and one write, the 12 bytes per attempt of the HBM
 // roofline model.
 #include "internal.h"
@@ -41,19 +43,21 @@ hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st) 
   return hipGetLastError();
 }
 
-constexpr int kPairBatch = 16;  // generator outputs per batch
+constexpr int kPairBatch = 8;  // generator outputs per batch
 
 // The next nb (<= kPairBatch) outputs of a lane's generator, in place: slot k
 // holds x_{n-624} before and x_n after; output i reads slots pos+i, pos+i+1
-// and pos+i+397 (mod 624), none of them written earlier in the batch.
-__device__ __forceinline__ void gen_batch(uint32_t *gen, int64_t n_lanes, int pos, int nb, uint32_t *u) {
+// and pos+i+397 (mod 624), none of them written earlier in the batch.  Row k
+// of the system's lanes starts at base + k * n_lanes (a wavefront-uniform
+// address); `lane` is the lane within the system.
+__device__ __forceinline__ void gen_batch(uint32_t *base, int64_t n_lanes, int lane, int pos, int nb, uint32_t *u) {
   uint32_t a[kPairBatch + 1], m[kPairBatch];
 #pragma unroll
   for (int i = 0; i <= kPairBatch; ++i)
     if (i <= nb) {
       int k = pos + i;
       if (k >= kMtN) k -= kMtN;
-      a[i] = gen[(int64_t)k * n_lanes];
+      a[i] = (base + (int64_t)k * n_lanes)[lane];
     }
 #pragma unroll
   for (int i = 0; i < kPairBatch; ++i)
@@ -61,7 +65,7 @@ __device__ __forceinline__ void gen_batch(uint32_t *gen, int64_t n_lanes, int po
       int k = pos + i + kMtM;
       if (k >= kMtN) k -= kMtN;
       if (k >= kMtN) k -= kMtN;
-      m[i] = gen[(int64_t)k * n_lanes];
+      m[i] = (base + (int64_t)k * n_lanes)[lane];
     }
 #pragma unroll
   for (int i = 0; i < kPairBatch; ++i)
@@ -69,17 +73,42 @@ __device__ __forceinline__ void gen_batch(uint32_t *gen, int64_t n_lanes, int po
       int k = pos + i;
       if (k >= kMtN) k -= kMtN;
       const uint32_t x = mt_next_word(a[i], a[i + 1], m[i]);
-      gen[(int64_t)k * n_lanes] = x;
+      (base + (int64_t)k * n_lanes)[lane] = x;
       u[i] = mt_temper(x);
     }
 }
 
-template <bool CELL, bool RING>
+// Record of template spin q (K4,4 cell templates, at most two neighbours
+// outside the cell), three LDS words:
+//   [0]  2J to the four partners in the other half of the cell, byte i for
+//        partner i (the sdot4 operand);
+//   [1]  h - sum of the in-slice J (int8) | J_tau << 8 | 2J_a << 16 | 2J_b << 24;
+//   [2]  word offset of outside neighbour a from q's word (int8) | its bit << 8
+//        | the same for b << 16 (2J = 0 when the neighbour does not exist).
+__device__ __forceinline__ void pair_record(const TmplSpin &ts, int q, uint32_t *r0, uint32_t *r1, uint32_t *r2) {
+  int sumJ = 0;
+  for (int j = 0; j < ts.deg; ++j) sumJ += ts.J[j];
+  uint32_t w1 = (uint32_t)(uint8_t)(int8_t)(ts.h - sumJ) | (uint32_t)(uint8_t)ts.Jtau << 8;
+  uint32_t w2 = 0;
+  for (int j = 4; j < 6; ++j) {
+    const int sh = 16 * (j - 4);
+    if (j < ts.deg) {
+      const int qq = ts.nbr[j];
+      w1 |= (uint32_t)(uint8_t)(int8_t)(2 * ts.J[j]) << (16 + 8 * (j - 4));
+      w2 |= ((uint32_t)(uint8_t)(int8_t)((qq >> 5) - (q >> 5)) | (uint32_t)(qq & 31) << 8) << sh;
+    }
+  }
+  *r0 = (uint32_t)ts.jpack;
+  *r1 = w1;
+  *r2 = w2;
+}
+
+template <bool RING>
 __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, uint32_t *pmt, int64_t n_lanes,
                                                      int32_t n_sweeps, int32_t init_mode, LadderArgs la) {
   extern __shared__ uint32_t lds[];
   const SysInfo sy = T.sys[blockIdx.x];
-  if ((sy.cell != 0) != CELL || (sy.ring != 0) != RING) return;  // the launch of its class takes it
+  if ((sy.ring != 0) != RING) return;  // the launch of its class takes it
   const int S = sy.S, M = sy.M, RS = sy.RS, WW = sy.WW, K = sy.K, P = M >> 1;
   const int PW = pair_walker_words(WW);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -106,6 +135,8 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   const bool ladder = la.swap_every > 0 && !init_mode;
   uint32_t *swin = lds + K * PW;
   int32_t *wat = (int32_t *)(swin + kMtN), *tof = wat + 256, *misc = tof + 256;
+  uint32_t *prec = swin + kLadderWords;  // template records, three arrays of S words
+  for (int q = tid; q < S; q += nthr) pair_record(T.tmpl[sy.tmpl0 + q], q, prec + q, prec + S + q, prec + 2 * S + q);
   if (ladder) {
     for (int j = tid; j < kMtN; j += nthr) swin[j] = St.swap_mt[(size_t)blockIdx.x * kMtN + j];
     for (int k = tid; k < K; k += nthr) {
@@ -117,9 +148,8 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   __syncthreads();
 
   // ---- this lane's generator and slices ----
-  uint32_t *gen = pmt + (live ? (int64_t)sy.pl0 + tid : 0);
+  uint32_t *gbase = pmt + sy.pl0;  // row 0 of the system's generator lanes
   int pos = init_mode ? 0 : (int)((2 * (int64_t)S * (1 + la.sweeps0)) % kMtN);
-  const TmplSpin *tm = T.tmpl + sy.tmpl0;
   int dE = 0, nfl = 0;  // sum of d over flips (the cost changes by 2d), flips
   int64_t n_rounds = 0;
   const int nsw = init_mode ? 1 : n_sweeps;
@@ -136,52 +166,69 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
         const uint32_t umask = ru < 0 ? 0u : ~0u, dmask = rd < 0 ? 0u : ~0u;
         const int ntau = (ru >= 0 ? 1 : 0) + (rd >= 0 ? 1 : 0);
         for (int wq = 0; wq * 32 < S; ++wq) {
-          const int nq = min(32, S - wq * 32);
-          uint32_t cur = rp[wq];
-          const uint32_t tu = up[wq] & umask, td = dn[wq] & dmask;
-          for (int n0 = 0; n0 < nq; n0 += kPairBatch) {
-            const int nb = min(kPairBatch, nq - n0);
-            uint32_t u[kPairBatch];
-            gen_batch(gen, n_lanes, pos, nb, u);
-            pos += nb;
-            if (pos >= kMtN) pos -= kMtN;
+          // every lane of the workgroup visits the same spin q at the same time:
+          // its template record is read once per wavefront, through the scalar cache
+          const int wqu = __builtin_amdgcn_readfirstlane(wq);
+          const int nq = min(32, S - wqu * 32);
+          uint32_t cur = rp[wqu];
+          const uint32_t tu = up[wqu] & umask, td = dn[wqu] & dmask;
+          // one attempt at bit b of the word, with uniform u
+          auto attempt = [&](const int b, const uint32_t u) {
+            const int q = wqu * 32 + b;
+            const uint32_t r0 = __builtin_amdgcn_readfirstlane(prec[q]);
+            const uint32_t r1 = __builtin_amdgcn_readfirstlane(prec[S + q]);
+            const uint32_t r2 = __builtin_amdgcn_readfirstlane(prec[2 * S + q]);
+            // h_eff = (h - sum J) + sum_j 2 J_j b_j + tau terms
+            const uint32_t nib = (cur >> ((b & ~3) ^ 4)) & 15u;  // the other half of the cell
+            const uint32_t spread = __umul24(nib, 0x00204081u) & 0x01010101u;
+            int hs = __builtin_amdgcn_sdot4((int)spread, (int)r0, (int)(int8_t)r1, false);
+            const int wa = (int)(int8_t)r2, wb = (int)(int8_t)(r2 >> 16);
+            const uint32_t na = wa == 0 ? cur : rp[wqu + wa];
+            const uint32_t nb2 = wb == 0 ? cur : rp[wqu + wb];
+            hs += (int)((na >> ((r2 >> 8) & 31u)) & 1u) * (int)(int8_t)(r1 >> 16);
+            hs += (int)((nb2 >> ((r2 >> 24) & 31u)) & 1u) * (int)(int8_t)(r1 >> 24);
+            const int jt = (int)(int8_t)(r1 >> 8);
+            hs += 2 * jt * (int)(((tu >> b) & 1u) + ((td >> b) & 1u)) - jt * ntau;
+            const int dn_ = -(int)((~cur >> b) & 1u);  // -1 for a spin down, 0 for up
+            const int d = (hs ^ dn_) - dn_;            // s * h_eff
+            const bool flip = u <= thw[d > 0 ? d : 0];
+            cur ^= flip ? 1u << b : 0u;
+            dE += flip ? d : 0;
+            nfl += flip ? 1 : 0;
+          };
 #pragma unroll
-            for (int i = 0; i < kPairBatch; ++i) {
-              if (i >= nb) break;
-              const int b = n0 + i;  // bit of the spin in the word
-              if (init_mode) {     // initial spin: the top bit of the output
-                cur |= (u[i] >> 31) << b;
-                continue;
-              }
-              const TmplSpin &ts = tm[wq * 32 + b];
-              // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms
-              int hs = ts.h;
-              if (CELL) {  // the other half of the spin's K4,4 cell: a nibble of this word
-                const uint32_t nib = (cur >> ((b & ~3) ^ 4)) & 15u;
-                const uint32_t spread = __umul24(nib, 0x00204081u) & 0x01010101u;
-                hs = __builtin_amdgcn_sdot4((int)spread, ts.jpack, hs, false);
-                hs -= ts.J[0] + ts.J[1] + ts.J[2] + ts.J[3];
-              }
+          for (int h = 0; h < 32 / kPairBatch; ++h) {
+            const int n0 = h * kPairBatch;
+            if (nq == 32) {  // a whole word: no guards
+              uint32_t u[kPairBatch];
+              gen_batch(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), kPairBatch, u);
+              pos += kPairBatch;
+              if (pos >= kMtN) pos -= kMtN;
 #pragma unroll
-              for (int j = CELL ? 4 : 0; j < kMaxDeg; ++j) {
-                if (j >= ts.deg) break;
-                const int qq = ts.nbr[j];
-                const int woff = (qq >> 5) - wq;
-                const uint32_t nw = woff == 0 ? cur : rp[wq + woff];
-                hs += (2 * (int)((nw >> (qq & 31)) & 1u) - 1) * ts.J[j];
+              for (int i = 0; i < kPairBatch; ++i) {
+                if (init_mode)
+                  cur |= (u[i] >> 31) << (n0 + i);  // initial spin: the top bit of the output
+                else
+                  attempt(n0 + i, u[i]);
               }
-              const int jt = ts.Jtau;
-              hs += 2 * jt * (int)(((tu >> b) & 1u) + ((td >> b) & 1u)) - jt * ntau;
-              const int dn_ = -(int)((~cur >> b) & 1u);  // -1 for a spin down, 0 for up
-              const int d = (hs ^ dn_) - dn_;            // s * h_eff
-              if (u[i] <= thw[d > 0 ? d : 0]) {
-                cur ^= 1u << b;
-                dE += d;
-                ++nfl;
+            } else if (n0 < nq) {  // the last, partial word of a slice
+              const int nb = min(kPairBatch, nq - n0);
+              uint32_t u[kPairBatch];
+              gen_batch(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), nb, u);
+              pos += nb;
+              if (pos >= kMtN) pos -= kMtN;
+#pragma unroll
+              for (int i = 0; i < kPairBatch; ++i) {
+                if (i < nb) {
+                  if (init_mode)
+                    cur |= (u[i] >> 31) << (n0 + i);
+                  else
+                    attempt(n0 + i, u[i]);
+                }
               }
             }
           }
-          rp[wq] = cur;
+          rp[wqu] = cur;
         }
       }
       __syncthreads();  // this parity's slices are final before the other parity reads them
@@ -230,11 +277,11 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   }
 }
 
-template <bool CELL, bool RING>
+template <bool RING>
 static hipError_t launch_pairs_variant(const DevTables &t, const DevState &s, uint32_t *pmt, int64_t n_lanes,
                                        int32_t n_sys, int32_t threads, size_t lds, int32_t n_sweeps,
                                        int32_t init_mode, LadderArgs la, hipStream_t st) {
-  auto kern = pairs_kernel<CELL, RING>;
+  auto kern = pairs_kernel<RING>;
   static bool lds_limit_set = false;
   if (!lds_limit_set && lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -245,20 +292,15 @@ static hipError_t launch_pairs_variant(const DevTables &t, const DevState &s, ui
   return hipGetLastError();
 }
 
-// classes: bit (2 cell + ring) set when some system is of that class; one
-// launch per class present (systems of other classes return at once).
+// classes: bit 0 set when some system has open slices, bit 1 when some has a
+// ring; one launch per class present (systems of the other class return at once).
 hipError_t launch_pairs(const DevTables &t, const DevState &s, uint32_t *pair_mt, int64_t n_lanes, int32_t n_sys,
                         int32_t threads, size_t lds, uint32_t classes, int32_t n_sweeps, int32_t init_mode,
                         LadderArgs la, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (e == hipSuccess && (classes & 8u))
-    e = launch_pairs_variant<true, true>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
-  if (e == hipSuccess && (classes & 4u))
-    e = launch_pairs_variant<true, false>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
-  if (e == hipSuccess && (classes & 2u))
-    e = launch_pairs_variant<false, true>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+  if (classes & 2u) e = launch_pairs_variant<true>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
   if (e == hipSuccess && (classes & 1u))
-    e = launch_pairs_variant<false, false>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
+    e = launch_pairs_variant<false>(t, s, pair_mt, n_lanes, n_sys, threads, lds, n_sweeps, init_mode, la, st);
   return e;
 }
 

@@ -16,7 +16,8 @@
 // word of 32 spins it is sweeping in a register, with the words of the slices
 // above and below.  The generators are interlaced in HBM ([624][lanes]: word
 // slot r of every generator in one row, so a wavefront's accesses are
-// coalesced) and updated in place 8 outputs at a time: per output one read of
+// coalesced) and updated in place 8 outputs at a time, the reads of a batch
+// issued while the previous batch's spins are attempted: per output one read of
 // slots n and n + 397 and one write, the 12 bytes per attempt of the HBM
 // roofline model.
 #include "internal.h"
@@ -45,34 +46,43 @@ hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st) 
 
 constexpr int kPairBatch = 8;  // generator outputs per batch
 
-// The next nb (<= kPairBatch) outputs of a lane's generator, in place: slot k
-// holds x_{n-624} before and x_n after; output i reads slots pos+i, pos+i+1
-// and pos+i+397 (mod 624), none of them written earlier in the batch.  Row k
-// of the system's lanes starts at base + k * n_lanes (a wavefront-uniform
-// address); `lane` is the lane within the system.
-__device__ __forceinline__ void gen_batch(uint32_t *base, int64_t n_lanes, int lane, int pos, int nb, uint32_t *u) {
+// A lane's generator is advanced in batches of kPairBatch outputs, in place:
+// slot k holds x_{n-624} before and x_n after; output i of a batch starting at
+// slot pos reads slots pos+i, pos+i+1 and pos+i+397 (mod 624), none of them
+// written earlier in the batch.  Row k of the system's lanes starts at base +
+// k * n_lanes (a wavefront-uniform address); `lane` is the lane within the
+// system.  The loads of a batch are issued one batch ahead (gen_load), so
+// their latency hides behind the previous batch's attempts; a batch's loads
+// touch no slot that the batch before it writes.
+struct GenBatch {
   uint32_t a[kPairBatch + 1], m[kPairBatch];
+};
+
+__device__ __forceinline__ void gen_load(const uint32_t *base, int64_t n_lanes, int lane, int pos, GenBatch &g) {
 #pragma unroll
-  for (int i = 0; i <= kPairBatch; ++i)
-    if (i <= nb) {
-      int k = pos + i;
-      if (k >= kMtN) k -= kMtN;
-      a[i] = (base + (int64_t)k * n_lanes)[lane];
-    }
+  for (int i = 0; i <= kPairBatch; ++i) {
+    int k = pos + i;
+    if (k >= kMtN) k -= kMtN;
+    g.a[i] = (base + (int64_t)k * n_lanes)[lane];
+  }
+#pragma unroll
+  for (int i = 0; i < kPairBatch; ++i) {
+    int k = pos + i + kMtM;
+    if (k >= kMtN) k -= kMtN;
+    if (k >= kMtN) k -= kMtN;
+    g.m[i] = (base + (int64_t)k * n_lanes)[lane];
+  }
+}
+
+// Outputs i < nb of the batch at pos: written back, tempered into u.
+__device__ __forceinline__ void gen_finish(uint32_t *base, int64_t n_lanes, int lane, int pos, int nb,
+                                           const GenBatch &g, uint32_t *u) {
 #pragma unroll
   for (int i = 0; i < kPairBatch; ++i)
     if (i < nb) {
-      int k = pos + i + kMtM;
-      if (k >= kMtN) k -= kMtN;
-      if (k >= kMtN) k -= kMtN;
-      m[i] = (base + (int64_t)k * n_lanes)[lane];
-    }
-#pragma unroll
-  for (int i = 0; i < kPairBatch; ++i)
-    if (i < nb) {
       int k = pos + i;
       if (k >= kMtN) k -= kMtN;
-      const uint32_t x = mt_next_word(a[i], a[i + 1], m[i]);
+      const uint32_t x = mt_next_word(g.a[i], g.a[i + 1], g.m[i]);
       (base + (int64_t)k * n_lanes)[lane] = x;
       u[i] = mt_temper(x);
     }
@@ -153,6 +163,8 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   int dE = 0, nfl = 0;  // sum of d over flips (the cost changes by 2d), flips
   int64_t n_rounds = 0;
   const int nsw = init_mode ? 1 : n_sweeps;
+  GenBatch gb;  // the loads of the next batch, issued one batch ahead
+  if (live) gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
   for (int sw = 0; sw < nsw; ++sw) {
     for (int par = 0; par < 2; ++par) {
       if (live) {
@@ -201,9 +213,10 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
             const int n0 = h * kPairBatch;
             if (nq == 32) {  // a whole word: no guards
               uint32_t u[kPairBatch];
-              gen_batch(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), kPairBatch, u);
+              gen_finish(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), kPairBatch, gb, u);
               pos += kPairBatch;
               if (pos >= kMtN) pos -= kMtN;
+              gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
 #pragma unroll
               for (int i = 0; i < kPairBatch; ++i) {
                 if (init_mode)
@@ -214,9 +227,10 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
             } else if (n0 < nq) {  // the last, partial word of a slice
               const int nb = min(kPairBatch, nq - n0);
               uint32_t u[kPairBatch];
-              gen_batch(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), nb, u);
+              gen_finish(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), nb, gb, u);
               pos += nb;
               if (pos >= kMtN) pos -= kMtN;
+              gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
 #pragma unroll
               for (int i = 0; i < kPairBatch; ++i) {
                 if (i < nb) {

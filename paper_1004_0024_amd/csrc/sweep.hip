@@ -188,6 +188,23 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     fmask[c] = (1 << (fw & 0xff)) - 1;
   }
 
+  // Range of the level offsets of each column slot over the wavefront: at
+  // level lv a lane is on row lv - f, so no lane of the wavefront can be on
+  // the first or last slice (whose halo copies a flip must keep) unless lv
+  // lies within [fmin, fmax] or [fmin + M - 1, fmax + M - 1].
+  int fmin[CPT], fspan[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    int lo = col[c] ? f[c] : (1 << 24), hi = col[c] ? f[c] : -(1 << 24);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o));
+      hi = max(hi, __shfl_xor(hi, o));
+    }
+    fmin[c] = __builtin_amdgcn_readfirstlane(lo);
+    fspan[c] = __builtin_amdgcn_readfirstlane(hi) - fmin[c];  // negative: no column in the wavefront
+  }
+
   // Generator: chain heads j < min(S, 227) go round-robin to the walker's
   // threads (head h of thread t is j = t + h*TPW; TPW*CPT >= S, so h < CPT);
   // a head makes words j, j+227, j+454 (< S) of each chunk.  The uniform
@@ -333,10 +350,13 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             else nfl += flip ? 1 : 0;
             dE += flip ? d : 0;
             if (TF) dB += flip ? dt : 0;
+            // wavefront-uniform: can any lane be on the first or last slice?
+            const bool edge = RING && ((unsigned)(lv - fmin[c]) <= (unsigned)fspan[c] ||
+                                       (unsigned)(lv - fmin[c] - (M - 1)) <= (unsigned)fspan[c]);
             if (flip) {
               const uint32_t bit = 1u << qb[c];
               atomicXor(own_p, bit);
-              if (RING) {  // keep the halo copy of the first / last slice
+              if (edge) {  // keep the halo copy of the first / last slice
                 if (mm == 0) atomicXor(own_p + WW, bit);
                 if (mm == M - 1) atomicXor(own_p - WW, bit);
               }

@@ -221,6 +221,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
       gqb[h][s] = (int)(fw >> 8);
       gqm[h][s] = (1 << (fw & 0xff)) - 1;
     }
+  // The look-back reads of every head run without a guard: for o = j + 227 s
+  // < heads + 454 they stay within [-624, Zg) of the ring (its shadow in
+  // front included), so only the words with o < S are computed and stored.
   auto gen_chunk = [&](int gslot, int chunk) {
     if (!live) return;
 #pragma unroll
@@ -231,10 +234,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int x = gslot + j + s * kMtLag;
-        if (j + s * kMtLag < S) {
-          a[s] = gring[x - kMtN];
-          b[s] = gring[x - kMtN + 1];
-        }
+        a[s] = gring[x - kMtN];
+        b[s] = gring[x - kMtN + 1];
       }
       uint32_t prev = gring[gslot + j - kMtLag];
 #pragma unroll

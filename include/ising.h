@@ -282,12 +282,14 @@ int32_t ising_trotter_weights(const double *beta, int32_t n, int32_t M, double g
  *     (slices of one parity share no edge, so they run side by side); the flip
  *     test, thresholds, acceptance variants, energies and swap rounds are those
  *     of the one-field form above;
- *   - after n outputs, word x_{n+i} (i < 624) of a generator is at row
- *     (n + i) mod 624 of its column: pair_mt is [624][lanes] (device, caller
- *     owned, ising_pairs_words elements).
- * Needs every system to have an even number of slices, K * M/2 <= 1024 and
- * its walkers' spins in LDS (ISING_E_RANGE otherwise), and the two-field form
- * off.  One workgroup sweeps a whole system and runs its swap rounds, so one
+ *   - after n outputs, word x_{n+i} (i < 624) of a generator is in its slot
+ *     k = (n + i) mod 624; slot k of lane l is element
+ *     ((k / 4) * lanes + l) * 4 + k % 4 of pair_mt (quads of slots, lanes
+ *     side by side: [156][lanes][4]; device, caller owned, 16-byte aligned,
+ *     ising_pairs_words elements).
+ * Needs every system to be a grid of K4,4 cells (so S is a multiple of 8),
+ * with an even number of slices, K * M/2 <= 1024 and its walkers' spins in LDS
+ * (ISING_E_RANGE otherwise), and the two-field form off.  One workgroup sweeps a whole system and runs its swap rounds, so one
  * launch (per template class) covers any number of sweeps.  The state's walker
  * streams (st->mt) are not used.                                              */
 int32_t ising_pairs_words(const ising_graph *g, int64_t *words);

@@ -347,16 +347,17 @@ class State:
 
     def pair_windows(self, system):
         """[lanes of `system`][624] words of its generator lanes, oldest first (each lane
-        of the system has delivered 2 S (1 + sweeps) outputs)."""
+        of the system has delivered 2 S (1 + sweeps) outputs).  Storage: slot k of lane l
+        at ((k // 4) * lanes + l) * 4 + k % 4."""
         l0 = 0
         for sysm in self.graph.systems[:system]:
             l0 += len(sysm.beta) * (int(sysm.M) // 2)
         sysm = self.graph.systems[system]
         lanes = len(sysm.beta) * (int(sysm.M) // 2)
-        cols = self.t["pair_mt"][: 624 * self.pair_lanes].view(624, self.pair_lanes)[:, l0:l0 + lanes]
-        a = cols.cpu().numpy().view(np.uint32)
+        blocks = self.t["pair_mt"][: 624 * self.pair_lanes].view(156, self.pair_lanes, 4)[:, l0:l0 + lanes, :]
+        a = blocks.cpu().numpy().view(np.uint32).transpose(1, 0, 2).reshape(lanes, 624)
         n = 2 * int(sysm.S) * (1 + self.sweeps)
-        return np.ascontiguousarray(a[(n + np.arange(624)) % 624].T)
+        return np.ascontiguousarray(a[:, (n + np.arange(624)) % 624])
 
     def refresh_energies(self):
         """Recompute the running cost and tau-bond sum of every walker from its spins."""

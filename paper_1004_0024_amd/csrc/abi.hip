@@ -1242,8 +1242,9 @@ extern "C" int32_t ising_pairs_init(const ising_graph *g, ising_state *st, uint3
   if (!pair_mt || !pair_seeds || !swap_seeds) return fail(ISING_E_INVAL, "pairs_init: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   DevState d = dev_state(st);
-  // seeds go to row 0; the seed kernel expands each lane's column
-  HIP_TRY(hipMemcpyAsync(pair_mt, pair_seeds, sizeof(uint32_t) * g->pair_lanes, hipMemcpyHostToDevice, s),
+  // seeds go to slot 0 of every lane; the seed kernel expands each lane's generator
+  HIP_TRY(hipMemcpy2DAsync(pair_mt, 4 * sizeof(uint32_t), pair_seeds, sizeof(uint32_t), sizeof(uint32_t),
+                           (size_t)g->pair_lanes, hipMemcpyHostToDevice, s),
           "pairs_init seeds");
   HIP_TRY(hipMemcpy2DAsync(st->swap_mt, kMtN * sizeof(uint32_t), swap_seeds, sizeof(uint32_t), sizeof(uint32_t),
                            (size_t)g->n_sys, hipMemcpyHostToDevice, s),

@@ -14,26 +14,33 @@
 // state and a three-word record per template spin (every lane visits the same
 // spin at the same time, so a record is one broadcast read).  A lane keeps the
 // word of 32 spins it is sweeping in a register, with the words of the slices
-// above and below.  The generators are interlaced in HBM ([624][lanes]: word
-// slot r of every generator in one row, so a wavefront's accesses are
-// coalesced) and updated in place 8 outputs at a time, the reads of a batch
-// issued while the previous batch's spins are attempted: per output one read of
-// slots n and n + 397 and one write, the 12 bytes per attempt of the HBM
-// roofline model.
+// above and below.  The generators are interlaced in HBM in quads of slots
+// ([156][lanes][4]: quad b of every lane side by side, so one 16-byte load per
+// lane covers a contiguous 1 KB per wavefront) and updated in place 8 outputs
+// (two quads) at a time, the reads of a batch issued while the previous
+// batch's spins are attempted: per output one read of slots n and n + 397 and
+// one write, the 12 bytes per attempt of the HBM roofline model.  Slices have
+// a multiple of 8 spins (K4,4 cells), so every batch is two whole, aligned
+// quads.
 #include "internal.h"
 #include "mt19937.h"
 #include "swap_round.h"
 
 namespace ising {
 
-// ---- seeding: row 0 of each lane holds the seed ---------------------------
+// ---- generator storage: slot k of lane l at ((k / 4) * n_lanes + l) * 4 + k % 4
+__host__ __device__ inline int64_t pair_slot(int k, int64_t lane, int64_t n_lanes) {
+  return ((int64_t)(k >> 2) * n_lanes + lane) * 4 + (k & 3);
+}
+
+// ---- seeding: slot 0 of each lane holds the seed --------------------------
 __global__ void pair_seed_kernel(uint32_t *pmt, int64_t n_lanes) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n_lanes) return;
-  uint32_t v = pmt[l];
+  uint32_t v = pmt[pair_slot(0, l, n_lanes)];
   for (int i = 1; i < kMtN; ++i) {
     v = mt_seed_step(v, (uint32_t)i);
-    pmt[(int64_t)i * n_lanes + l] = v;
+    pmt[pair_slot(i, l, n_lanes)] = v;
   }
 }
 
@@ -44,48 +51,57 @@ hipError_t launch_pair_seed(uint32_t *pair_mt, int64_t n_lanes, hipStream_t st) 
   return hipGetLastError();
 }
 
-constexpr int kPairBatch = 8;  // generator outputs per batch
+constexpr int kPairBatch = 8;                 // generator outputs per batch: two quads
+constexpr int kPairQuads = kMtN / 4;          // 156
 
-// A lane's generator is advanced in batches of kPairBatch outputs, in place:
-// slot k holds x_{n-624} before and x_n after; output i of a batch starting at
-// slot pos reads slots pos+i, pos+i+1 and pos+i+397 (mod 624), none of them
-// written earlier in the batch.  Row k of the system's lanes starts at base +
-// k * n_lanes (a wavefront-uniform address); `lane` is the lane within the
-// system.  The loads of a batch are issued one batch ahead (gen_load), so
-// their latency hides behind the previous batch's attempts; a batch's loads
-// touch no slot that the batch before it writes.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A lane's generator is advanced 8 outputs at a time, in place: slot k holds
+// x_{n-624} before and x_n after; output i of the batch at slot pos (a
+// multiple of 8) reads slots pos+i, pos+i+1 and pos+i+397 (mod 624), none of
+// them written earlier in the batch.  pos + 397 = 4 (pos/4 + 99) + 1, so the
+// look-back words are words 1..3 of quad pos/4 + 99, all of the next quad and
+// word 0 of the one after.  The loads of a batch are issued one batch ahead
+// (gen_load), so their latency hides behind the previous batch's attempts; a
+// batch's loads touch no slot that the batch before it writes.
 struct GenBatch {
-  uint32_t a[kPairBatch + 1], m[kPairBatch];
+  u32x4 a0, a1, m0, m1;  // slots pos..pos+7; look-back quads pos/4 + 99 and + 100
+  uint32_t a8, m8;       // slot pos+8; look-back word 0 of quad pos/4 + 101
 };
 
-__device__ __forceinline__ void gen_load(const uint32_t *base, int64_t n_lanes, int lane, int pos, GenBatch &g) {
-#pragma unroll
-  for (int i = 0; i <= kPairBatch; ++i) {
-    int k = pos + i;
-    if (k >= kMtN) k -= kMtN;
-    g.a[i] = (base + (int64_t)k * n_lanes)[lane];
-  }
-#pragma unroll
-  for (int i = 0; i < kPairBatch; ++i) {
-    int k = pos + i + kMtM;
-    if (k >= kMtN) k -= kMtN;
-    if (k >= kMtN) k -= kMtN;
-    g.m[i] = (base + (int64_t)k * n_lanes)[lane];
-  }
+// quad b of this lane: lane0 points at quad 0 of the lane (4 words)
+__device__ __forceinline__ const uint32_t *pair_quad(const uint32_t *lane0, int64_t n_lanes, int b) {
+  return lane0 + (int64_t)b * n_lanes * 4;
 }
 
-// Outputs i < nb of the batch at pos: written back, tempered into u.
-__device__ __forceinline__ void gen_finish(uint32_t *base, int64_t n_lanes, int lane, int pos, int nb,
-                                           const GenBatch &g, uint32_t *u) {
+__device__ __forceinline__ int quad_add(int b, int d) {
+  b += d;
+  return b >= kPairQuads ? b - kPairQuads : b;
+}
+
+__device__ __forceinline__ void gen_load(const uint32_t *lane0, int64_t n_lanes, int pos, GenBatch &g) {
+  const int b = pos >> 2;
+  g.a0 = *(const u32x4 *)pair_quad(lane0, n_lanes, b);
+  g.a1 = *(const u32x4 *)pair_quad(lane0, n_lanes, quad_add(b, 1));
+  g.a8 = pair_quad(lane0, n_lanes, quad_add(b, 2))[0];
+  g.m0 = *(const u32x4 *)pair_quad(lane0, n_lanes, quad_add(b, 99));
+  g.m1 = *(const u32x4 *)pair_quad(lane0, n_lanes, quad_add(b, 100));
+  g.m8 = pair_quad(lane0, n_lanes, quad_add(b, 101))[0];
+}
+
+// The 8 outputs of the batch at pos: written back, tempered into u.
+__device__ __forceinline__ void gen_finish(uint32_t *lane0, int64_t n_lanes, int pos, const GenBatch &g, uint32_t *u) {
+  const uint32_t a[9] = {g.a0.x, g.a0.y, g.a0.z, g.a0.w, g.a1.x, g.a1.y, g.a1.z, g.a1.w, g.a8};
+  const uint32_t m[8] = {g.m0.y, g.m0.z, g.m0.w, g.m1.x, g.m1.y, g.m1.z, g.m1.w, g.m8};
+  uint32_t x[8];
 #pragma unroll
-  for (int i = 0; i < kPairBatch; ++i)
-    if (i < nb) {
-      int k = pos + i;
-      if (k >= kMtN) k -= kMtN;
-      const uint32_t x = mt_next_word(g.a[i], g.a[i + 1], g.m[i]);
-      (base + (int64_t)k * n_lanes)[lane] = x;
-      u[i] = mt_temper(x);
-    }
+  for (int i = 0; i < 8; ++i) {
+    x[i] = mt_next_word(a[i], a[i + 1], m[i]);
+    u[i] = mt_temper(x[i]);
+  }
+  const int b = pos >> 2;
+  *(u32x4 *)pair_quad(lane0, n_lanes, b) = u32x4{x[0], x[1], x[2], x[3]};
+  *(u32x4 *)pair_quad(lane0, n_lanes, quad_add(b, 1)) = u32x4{x[4], x[5], x[6], x[7]};
 }
 
 // Record of template spin q (K4,4 cell templates, at most two neighbours
@@ -158,13 +174,13 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   __syncthreads();
 
   // ---- this lane's generator and slices ----
-  uint32_t *gbase = pmt + sy.pl0;  // row 0 of the system's generator lanes
+  uint32_t *glane = pmt + ((int64_t)sy.pl0 + (live ? tid : 0)) * 4;  // this lane's quad 0
   int pos = init_mode ? 0 : (int)((2 * (int64_t)S * (1 + la.sweeps0)) % kMtN);
   int dE = 0, nfl = 0;  // sum of d over flips (the cost changes by 2d), flips
   int64_t n_rounds = 0;
   const int nsw = init_mode ? 1 : n_sweeps;
   GenBatch gb;  // the loads of the next batch, issued one batch ahead
-  if (live) gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
+  if (live) gen_load(glane, n_lanes, __builtin_amdgcn_readfirstlane(pos), gb);
   for (int sw = 0; sw < nsw; ++sw) {
     for (int par = 0; par < 2; ++par) {
       if (live) {
@@ -211,34 +227,18 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
 #pragma unroll
           for (int h = 0; h < 32 / kPairBatch; ++h) {
             const int n0 = h * kPairBatch;
-            if (nq == 32) {  // a whole word: no guards
+            if (nq == 32 || n0 < nq) {  // whole blocks: S is a multiple of 8
               uint32_t u[kPairBatch];
-              gen_finish(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), kPairBatch, gb, u);
+              gen_finish(glane, n_lanes, __builtin_amdgcn_readfirstlane(pos), gb, u);
               pos += kPairBatch;
               if (pos >= kMtN) pos -= kMtN;
-              gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
+              gen_load(glane, n_lanes, __builtin_amdgcn_readfirstlane(pos), gb);
 #pragma unroll
               for (int i = 0; i < kPairBatch; ++i) {
                 if (init_mode)
                   cur |= (u[i] >> 31) << (n0 + i);  // initial spin: the top bit of the output
                 else
                   attempt(n0 + i, u[i]);
-              }
-            } else if (n0 < nq) {  // the last, partial word of a slice
-              const int nb = min(kPairBatch, nq - n0);
-              uint32_t u[kPairBatch];
-              gen_finish(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), nb, gb, u);
-              pos += nb;
-              if (pos >= kMtN) pos -= kMtN;
-              gen_load(gbase, n_lanes, tid, __builtin_amdgcn_readfirstlane(pos), gb);
-#pragma unroll
-              for (int i = 0; i < kPairBatch; ++i) {
-                if (i < nb) {
-                  if (init_mode)
-                    cur |= (u[i] >> 31) << (n0 + i);
-                  else
-                    attempt(n0 + i, u[i]);
-                }
               }
             }
           }

@@ -22,11 +22,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak, TFLOP/s
 BYTES_PER_ATTEMPT = 12         # spin r+w 2 B, field r+w 2 B, MT word r+w 8 B
+# ALU model of an attempt: 32-bit lane operations (MT19937 word ~14, flip test ~7, update ~32, loop
+# and addresses), against the chip's 32-bit integer lane-op rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+LANE_OPS_PER_ATTEMPT = 60
+LANE_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
 # HBM bytes per sweep launch on the throughput workload, from rocprofv3 FETCH_SIZE (x2.00) and
 # WRITE_SIZE (x1.00) scaled against a device copy of known size (sweep kernel unchanged since).
 SWEEP_TRAFFIC_BYTES = {"B": 157.0e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
+
+
+def alu_roofline(attempts_per_s):
+    """The ALU side of the same model (the sweep is bound by integer arithmetic as much as by
+    bytes): lane operations per second at LANE_OPS_PER_ATTEMPT against the chip's peak."""
+    achieved = LANE_OPS_PER_ATTEMPT * attempts_per_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": LANE_OPS_PEAK_T, "unit": "T lane-ops/s",
+            "frac": achieved / LANE_OPS_PEAK_T, "lane_ops_per_attempt": LANE_OPS_PER_ATTEMPT}
 
 
 def cpu_baseline(wl, budget_s=20.0):
@@ -138,7 +150,8 @@ def two_field_leg(steps, gamma=1.0):
             "value": g.attempts_per_sweep * n_sw * steps / (ms / 1e3), "unit": "spin-flip attempts/s",
             "sweep_kernel_ms": {"mean": avg, "min": min(sweep_ms), "max": max(sweep_ms)},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT},
+                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT,
+                         "alu": alu_roofline(g.attempts_per_sweep / (avg / 1e3))},
             "launch_shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")} for b in g.buckets()],
             "flip_rate": stats["flips"] / max(1, stats["attempts"]),
             "wave_steps_with_flip": stats["wave_flip_steps"] / max(1, stats["wave_steps"])}
@@ -178,7 +191,7 @@ def pairs_leg(name, n_sweeps, reps):
             "value": attempts / (avg / 1e3), "unit": "spin-flip attempts/s",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT,
-                         "kernel": "pairs_kernel"},
+                         "kernel": "pairs_kernel", "alu": alu_roofline(attempts / (avg / 1e3))},
             "flip_rate": stats["flips"] / max(1, g.attempts_per_sweep * st.sweeps)}
 
 
@@ -396,7 +409,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": SWEEP_TRAFFIC_BYTES.get(args.config), "traffic_unit": "HBM bytes per launch",
                      "kernel": "sweep_kernel", "kernel_avg_ms": avg_sweep_s * 1e3,
-                     "bytes_per_attempt": BYTES_PER_ATTEMPT},
+                     "bytes_per_attempt": BYTES_PER_ATTEMPT,
+                     "alu": alu_roofline(g.attempts_per_sweep / avg_sweep_s)},
         "wall_s_timed": wall,
         "graph_replay": {"ms_per_step": graph_ms, "value": g.attempts_per_sweep * n_sw / (graph_ms / 1e3)},
         "launch_shapes": tuned,

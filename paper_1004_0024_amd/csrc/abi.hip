@@ -671,11 +671,13 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
     double *bt = (double *)(host.data() + L.beta);
     for (auto &h : hs)
       for (int32_t k = 0; k < h.K; ++k) {
-        rc = ising_threshold_row(h.beta[k], kThrRow - 1, thr);
+        uint32_t row[kThrRow - kThrZero];
+        rc = ising_threshold_row(h.beta[k], kThrRow - kThrZero - 1, row);
         if (rc) {
           delete g;
           return rc;
         }
+        for (int32_t i = 0; i < kThrRow; ++i) thr[i] = i <= kThrZero ? 0xffffffffu : row[i - kThrZero];
         thr += kThrRow;
         *bt++ = h.beta[k];
         g->slot_beta.push_back(h.beta[k]);
@@ -780,8 +782,10 @@ extern "C" int32_t ising_set_acceptance(ising_graph *g, int32_t kind, void *stre
   if (!g) return fail(ISING_E_INVAL, "set_acceptance: NULL graph");
   std::vector<uint32_t> rows((size_t)g->slots * kThrRow);
   for (size_t k = 0; k < g->slot_beta.size(); ++k) {
-    const int32_t rc = ising_acceptance_row(g->slot_beta[k], kThrRow - 1, kind, rows.data() + k * kThrRow);
+    uint32_t row[kThrRow - kThrZero];
+    const int32_t rc = ising_acceptance_row(g->slot_beta[k], kThrRow - kThrZero - 1, kind, row);
     if (rc) return rc;
+    for (int32_t i = 0; i < kThrRow; ++i) rows[k * kThrRow + i] = i <= kThrZero ? 0xffffffffu : row[i - kThrZero];
   }
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync((void *)g->dev.thr, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st),

@@ -8,7 +8,12 @@ namespace ising {
 constexpr int kMtN = 624;       // MT19937 words
 constexpr int kMtM = 397;       // MT19937 middle offset
 constexpr int kMtLag = 227;     // kMtN - kMtM: words generated without a chain
-constexpr int kThrRow = 64;     // threshold words per temperature slot (d = 0..63)
+// Threshold row of a temperature slot on the device: entry kThrZero + d for
+// d = -64..63 (every entry with d <= 0 is 0xffffffff: such a flip always
+// passes), so the sweep indexes it with d directly.
+constexpr int kThrRow = 128;
+constexpr int kThrZero = 64;
+constexpr int kPairThrRow = 64;  // the layer-pair kernel keeps entries d = 0..63 of the row
 constexpr int kMaxDeg = 8;      // in-slice neighbours in a template record
 
 // One system, as the kernels see it.
@@ -176,7 +181,7 @@ hipError_t launch_pairs(const DevTables &t, const DevState &s, uint32_t *pair_mt
 // threshold row, reduction words; odd, so the walkers of a wavefront use
 // different banks.
 __host__ __device__ inline int32_t pair_walker_words(int32_t WW) {
-  const int32_t w = WW + kThrRow + 4;
+  const int32_t w = WW + kPairThrRow + 4;
   return w | 1;
 }
 

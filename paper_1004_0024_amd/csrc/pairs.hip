@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   const bool live = w < K;
   uint32_t *slot = lds + (live ? w : 0) * PW;
   const uint32_t *thw = slot + WW;
-  int32_t *acc = (int32_t *)(slot + WW + kThrRow);
+  int32_t *acc = (int32_t *)(slot + WW + kPairThrRow);
 
   // ---- load the walkers' spins, threshold rows and running costs ----
   for (int i = tid; i < K * WW; i += nthr) {
@@ -150,13 +150,13 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
     lds[ww * PW + j] = init_mode ? 0u : St.spins[sy.spin_word0 + (int64_t)ww * WW + j];
   }
   if (!init_mode)
-    for (int i = tid; i < K * kThrRow; i += nthr) {
-      const int ww = i / kThrRow, j = i - ww * kThrRow;
+    for (int i = tid; i < K * kPairThrRow; i += nthr) {  // entries d = 0..63 of the slot's row
+      const int ww = i / kPairThrRow, j = i - ww * kPairThrRow;
       const int sl = St.temp_of[sy.walker0 + ww];
-      lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + sl) * kThrRow + j];
+      lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + sl) * kThrRow + kThrZero + j];
     }
   for (int i = tid; i < K * 4; i += nthr)
-    lds[(i >> 2) * PW + WW + kThrRow + (i & 3)] =
+    lds[(i >> 2) * PW + WW + kPairThrRow + (i & 3)] =
         ((i & 3) == 0 && !init_mode) ? (uint32_t)St.energy[sy.walker0 + (i >> 2)] : 0u;
   const bool ladder = la.swap_every > 0 && !init_mode;
   uint32_t *swin = lds + K * PW;
@@ -253,12 +253,12 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
       __syncthreads();
       if (tid == 0)
         ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
-                          WW + kThrRow);
+                          WW + kPairThrRow);
       ++n_rounds;
       __syncthreads();
-      for (int i = tid; i < K * kThrRow; i += nthr) {
-        const int ww = i / kThrRow, j = i - ww * kThrRow;
-        lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + tof[ww]) * kThrRow + j];
+      for (int i = tid; i < K * kPairThrRow; i += nthr) {
+        const int ww = i / kPairThrRow, j = i - ww * kPairThrRow;
+        lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + tof[ww]) * kThrRow + kThrZero + j];
       }
       __syncthreads();
     }
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
   }
   if (!init_mode && tid < K) {
     const int r = sy.walker0 + tid;
-    const int32_t *a = (const int32_t *)(lds + tid * PW + WW + kThrRow);
+    const int32_t *a = (const int32_t *)(lds + tid * PW + WW + kPairThrRow);
     St.energy[r] = a[0];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
   }

@@ -37,8 +37,9 @@
 //    g mod depth, where it waits until the column reaches that slice (slot k
 //    of a queue is 64 words after slot k - 1, so a queue sits in one bank and
 //    the 64 columns of a wavefront use 64 different banks);
-//  - the walker's threshold row thr[d] = ceil(2^32 exp(-2 beta d)) - 1, or in
-//    the two-field form the row of its slot over (d_sp, d_t).
+//  - the walker's threshold row, entry kThrZero + d = ceil(2^32 exp(-2 beta d))
+//    - 1 (all ones for d <= 0), or in the two-field form the row of its slot
+//    over (d_sp, d_t).
 // Two-field form (the QMC models' separate fields, Sections 2.1-2.2): the
 // in-slice part of the field (with h) and the tau part are kept apart, d_sp =
 // s h_sp and d_t = s h_tau, and the threshold is looked up at the pair; the
@@ -99,6 +100,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   }
   const int SWW = WW + 2 * RS;  // spin rows with the two halo rows
   const int TRW = TF ? T.qrow : kThrRow;  // threshold row words
+  constexpr int SG = TF ? 1 : -1;         // sign of the accumulated field
   constexpr int NACC = TF ? 5 : 4;        // reduction words
   for (int i = tid; i < nw * SWW; i += nthr) {
     const int w = i / SWW, j = i - w * SWW;
@@ -166,7 +168,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     if (CELL) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) sumJ += ts.J[j];
-      jpack[c] = ts.jpack;
+      uint32_t jp = 0;  // the partners' 2J bytes, times SG
+#pragma unroll
+      for (int j = 0; j < 4; ++j) jp |= (uint32_t)(uint8_t)(int8_t)(SG * (int)(int8_t)(ts.jpack >> (8 * j))) << (8 * j);
+      jpack[c] = (int)jp;
     } else {
       jpack[c] = 0;
     }
@@ -175,14 +180,16 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
       const int qq = ts.nbr[(CELL ? 4 : 0) + j];
       xoff[c][j] = (qq >> 5) - qo[c];
       xbit[c][j] = qq & 31;
-      xj2[c][j] = 2 * (int)ts.J[(CELL ? 4 : 0) + j];
+      xj2[c][j] = SG * 2 * (int)ts.J[(CELL ? 4 : 0) + j];
       sumJ += ts.J[(CELL ? 4 : 0) + j];
     }
-    jt[c] = ts.Jtau;
+    jt[c] = SG * (int)ts.Jtau;
     f[c] = col[c] ? (int)ts.f : (1 << 24);  // a column without a spin is never active
     // h_eff = h + sum_j J_j (2 b_j - 1) + tau terms: the constant part is `base`
-    // (in the two-field form without the tau terms, which form h_tau).
-    base[c] = (int)ts.h - sumJ - (RING && !TF ? 2 * (int)ts.Jtau : 0);
+    // (in the two-field form without the tau terms, which form h_tau).  The
+    // one-field form accumulates -h_eff (every coefficient negated), so that
+    // d = s h_eff comes from the spin's bit with one sign extension.
+    base[c] = SG * ((int)ts.h - sumJ - (RING && !TF ? 2 * (int)ts.Jtau : 0));
     const uint32_t fw = T.fifo[sy.tmpl0 + qq0];
     fb[c] = (int)(fw >> 8);
     fmask[c] = (1 << (fw & 0xff)) - 1;
@@ -318,29 +325,29 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             int ht = 0;  // tau part of the field (two-field form)
             if (RING) {
               if (TF)
-                ht = 2 * jt[c] * (bp + bn) - 2 * jt[c];
+                ht = __mul24(2 * jt[c], bp + bn) - 2 * jt[c];
               else
-                hs += 2 * jt[c] * (bp + bn);
+                hs += __mul24(2 * jt[c], bp + bn);
             } else {
               const int jp = mm > 0 ? jt[c] : 0, jn = mm < M - 1 ? jt[c] : 0;
               if (TF)
-                ht = jp * (2 * bp - 1) + jn * (2 * bn - 1);
+                ht = __mul24(jp, 2 * bp - 1) + __mul24(jn, 2 * bn - 1);
               else
-                hs += jp * (2 * bp - 1) + jn * (2 * bn - 1);
+                hs += __mul24(jp, 2 * bp - 1) + __mul24(jn, 2 * bn - 1);
             }
-            // d = s_i * h_eff_i (flipping costs 2d): with dn = -1 for a spin
-            // down and 0 for up, d = (hs ^ dn) - dn
-            const int dn = __builtin_amdgcn_sbfe((int)~own, (unsigned)qb[c], 1u);
+            // d = s_i * h_eff_i (flipping costs 2d)
             int d, dt = 0;
             uint32_t thv;
-            if (TF) {
+            if (TF) {  // with dn = -1 for a spin down and 0 for up, d = (h ^ dn) - dn
+              const int dn = __builtin_amdgcn_sbfe((int)~own, (unsigned)qb[c], 1u);
               const int dsp = (hs ^ dn) - dn;
               dt = (ht ^ dn) - dn;
               d = dsp + dt;
               thv = thw[dsp * qwt + dt + qoff];
-            } else {
-              d = (hs ^ dn) - dn;
-              thv = thw[d > 0 ? d : 0];
+            } else {  // hs = -h_eff; with up = -1 for a spin up and 0 for down, d = (hs ^ up) - up
+              const int up = __builtin_amdgcn_sbfe((int)own, (unsigned)qb[c], 1u);
+              d = (hs ^ up) - up;
+              thv = thw[d + kThrZero];
             }
             const uint32_t u = mt_temper(u0);
             const bool le = u <= thv;

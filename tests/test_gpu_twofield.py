@@ -167,3 +167,28 @@ def test_two_field_config_B_full_size_sampled():
     wl.systems = [dataclasses.replace(s, J_tau=np.ones(s.S, np.int8)) for s in wl.systems]
     a, c = _weights(wl, 1.0)
     _run(wl, [0, 255], a, c, [1, 2])
+
+
+def test_switch_to_two_field_mid_run():
+    """One-field sweeps, then the two-field form on the same state (tau-bond sums refreshed),
+    against oracle chains that switch at the same sweep."""
+    wl = Workload("switch", [make_chimera_system(2, 8, 53, 8), make_chimera_system(4, 4, 54, 6)], 0, 1)
+    say(wl.name, "one-field then two-field")
+    g, st = make_state(wl)
+    chains = chains_for(wl, [0, 1])
+    st.sweep(7, 1)
+    for s, ch in enumerate(chains):
+        ch.sweeps(7, 1)
+        compare_system(st, s, ch, "one-field")
+    a, c = _weights(wl, 0.8)
+    g.set_two_field(a, c)
+    st.refresh_energies()
+    for s, ch in enumerate(chains):
+        b0, b1 = int(wl.walker_base[s]), int(wl.walker_base[s + 1])
+        ch.set_two_field(oracle.tau_edge_mask(wl.systems[s]), a[b0:b1], c[b0:b1])
+        _compare(st, s, ch, "after the switch")
+    for n in (1, 6):
+        st.sweep(n, 1)
+        for s, ch in enumerate(chains):
+            ch.sweeps(n, 1)
+            _compare(st, s, ch, f"two-field, {st.sweeps} sweeps")

@@ -268,6 +268,17 @@ def learned_leg(ess_steps, train_rows=1 << 20):
                         "coldest_mean_energy": float(r["e"][:, 31::32].mean())}
         if "acceptance" in r:
             chains[name]["cell_acceptance" if n is not None else "cell_changed"] = r["acceptance"]
+    # cell-move cadence: one pass of learned (or heat-bath) cell moves after every k-th step
+    cell_cadence = []
+    for every in (2, 4, 8):
+        row = {"cell_every": every}
+        for name, n, hb in (("learned", net, False), ("heatbath", None, True)):
+            s2 = pa.State(g).copy_from(base)
+            r = learn.run(s2, ess_steps // 2, n, pass0=2000, heatbath=hb, cell_every=every)
+            e = learn.ess_summary(g, r["e"])
+            row[name] = {"ms_per_step": r["ms"] / (ess_steps // 2), "ess_coldest": e["coldest_total"],
+                         "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3)}
+        cell_cadence.append(row)
     # swap cadence (it changes the chain; the objective is effective samples per second)
     cadence = []
     for every in (1, 2, 4, 8):
@@ -280,6 +291,7 @@ def learned_leg(ess_steps, train_rows=1 << 20):
     return {
         "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": 3000,
         "swap_cadence": cadence,
+        "cell_cadence": cell_cadence,
         "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems",
         "train": {"rows": int(x.shape[0]), "batch": 4096, "adam_steps": int(len(losses)),
                   "loss_untrained": loss0, "loss_last": float(losses[-1]), "seconds": train_s},

@@ -57,11 +57,11 @@ def train(net, x, y, batch=4096, epochs=2, lr=1e-3):
     return torch.stack([l.reshape(()) for l in losses]).cpu().numpy()
 
 
-def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False):
+def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False, cell_every=1):
     """`steps` steps of the chain: a sweep and its swap round, then, with a network, one
     pass of learned cell moves, or with `heatbath`, one pass of exact heat-bath cell
-    moves.  Returns slot energies [steps, slots] (host), GPU ms and the fraction of cells
-    accepted (learned) or changed (heat-bath)."""
+    moves, after every `cell_every`-th step.  Returns slot energies [steps, slots] (host),
+    GPU ms and the fraction of cells accepted (learned) or changed (heat-bath)."""
     import torch
     g = state.graph
     e = torch.zeros((steps, g.slots), dtype=torch.int32, device=g.tables.device)
@@ -72,10 +72,11 @@ def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False):
     t0.record()
     for t in range(steps):
         state.sweep(1, swap_every)
-        if net is not None:
-            state.propose_cells(net, key, pass0 + t, moves)
-        elif heatbath:
-            state.heatbath_cells(key, pass0 + t, moves)
+        if (t + 1) % cell_every == 0:
+            if net is not None:
+                state.propose_cells(net, key, pass0 + t, moves)
+            elif heatbath:
+                state.heatbath_cells(key, pass0 + t, moves)
         state.record(e[t])
     t1.record()
     torch.cuda.synchronize()

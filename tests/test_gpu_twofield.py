@@ -192,3 +192,23 @@ def test_switch_to_two_field_mid_run():
         for s, ch in enumerate(chains):
             ch.sweeps(n, 1)
             _compare(st, s, ch, f"two-field, {st.sweeps} sweeps")
+
+
+def test_two_field_autotune_keeps_the_chain():
+    """Launch shapes tuned in the two-field form (no whole-ladder shapes) leave the chain unchanged."""
+    import paper_1004_0024_amd as pa
+    wl = Workload("tune two-field", [make_chimera_system(4, 8, 55, 8), make_chimera_system(2, 8, 56, 16)], 0, 1)
+    say(wl.name)
+    a, c = _weights(wl, 0.6)
+    g = pa.Graph(wl.systems)
+    g.set_two_field(a, c)
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    rows = g.autotune(scratch, reps=2)
+    assert len(rows) > 4 and all(r["ns_per_sweep"] > 0 for r in rows)
+    assert not any(b["ladder"] for b in g.buckets())
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    chains = _two_field_chains(wl, [0, 1], a, c)
+    st.sweep(6, 1)
+    for s, ch in enumerate(chains):
+        ch.sweeps(6, 1)
+        _compare(st, s, ch, "after autotune")

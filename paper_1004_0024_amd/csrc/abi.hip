@@ -147,6 +147,7 @@ struct SysHost {
   int32_t pc[5] = {0, 0, 0, 0, 0};
   std::vector<TmplSpin> tmpl;
   std::vector<uint32_t> fifo;  // (queue base << 8) | log2(depth) per template spin
+  std::vector<uint16_t> lanes;  // sweep lane position -> template spin, by level offset
   std::vector<uint32_t> cellrec;  // grid templates: kCellRecWords words per template cell
   std::vector<double> beta;
 };
@@ -258,11 +259,18 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
   }
   if (F > 255) return fail(ISING_E_RANGE, "system %d: schedule depth %d exceeds 255", idx, F);
   out.F = F;
+  // Sweep lanes: the columns in order of their level offset (ties in index
+  // order).  A column is busy for M consecutive levels from f(q), so a
+  // wavefront whose columns share nearly one offset idles on few levels; in
+  // index order a wavefront of a Chimera template spans offsets y .. y + L.
+  out.lanes.resize(S);
+  for (int32_t q = 0; q < S; ++q) out.lanes[q] = (uint16_t)q;
+  std::stable_sort(out.lanes.begin(), out.lanes.end(), [&](uint16_t a, uint16_t b) { return f[a] < f[b]; });
   // Uniform queues.  Slot k of column q's queue is word base(q) + 64 k: a
-  // queue lives in one LDS bank.  The columns of a 64-column group (the lanes
-  // of one wavefront) take 64 different banks, bank (q + r_w) mod 64 with a
-  // rotation r_w per group chosen so that the banks' stacks stay even; a
-  // wavefront's reads and writes of the queues then never conflict.
+  // queue lives in one LDS bank.  The columns of 64 consecutive lane positions
+  // (one wavefront) take 64 different banks, bank (l + r_w) mod 64 for
+  // position l of the group, with a rotation r_w per group chosen so that the
+  // banks' stacks stay even; a wavefront's queue reads then never conflict.
   out.fifo.assign(S, 0);
   {
     int32_t height[64] = {0};
@@ -271,11 +279,11 @@ static int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &ou
       for (int32_t r = 0; r < 64; ++r) {
         int32_t hmax = 0;
         for (int32_t l = 0; l < 64 && g0 + l < S; ++l)
-          hmax = std::max(hmax, height[(l + r) & 63] + fifo_depth(f[g0 + l]));
+          hmax = std::max(hmax, height[(l + r) & 63] + fifo_depth(f[out.lanes[g0 + l]]));
         if (hmax < best_h) best_h = hmax, best_r = r;
       }
       for (int32_t l = 0; l < 64 && g0 + l < S; ++l) {
-        const int32_t q = g0 + l, b = (l + best_r) & 63, dq = fifo_depth(f[q]);
+        const int32_t q = out.lanes[g0 + l], b = (l + best_r) & 63, dq = fifo_depth(f[q]);
         int32_t lg = 0;
         while ((1 << lg) < dq) ++lg;
         out.fifo[q] = ((uint32_t)(height[b] * 64 + b) << 8) | (uint32_t)lg;
@@ -405,7 +413,7 @@ struct ising_graph {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sys, tmpl, fifo, thr, beta, tiles, wsys, cells, rtiles, cellrec, qthr, qa, qc, total;
+  size_t sys, tmpl, fifo, lanes, thr, beta, tiles, wsys, cells, rtiles, cellrec, qthr, qa, qc, total;
 };
 
 // Device tables.  Room for one tile per walker, so any launch shape can be
@@ -421,6 +429,8 @@ static Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n
   o = align256(o + sizeof(TmplSpin) * n_tmpl);
   L.fifo = o;
   o = align256(o + sizeof(uint32_t) * n_tmpl);
+  L.lanes = o;
+  o = align256(o + sizeof(uint16_t) * n_tmpl);
   L.thr = o;
   o = align256(o + sizeof(uint32_t) * kThrRow * slots);
   L.beta = o;
@@ -685,9 +695,12 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   }
   {
     uint32_t *fo = (uint32_t *)(host.data() + L.fifo);
+    uint16_t *lo = (uint16_t *)(host.data() + L.lanes);
     for (auto &h : hs) {
       memcpy(fo, h.fifo.data(), sizeof(uint32_t) * h.S);
+      memcpy(lo, h.lanes.data(), sizeof(uint16_t) * h.S);
       fo += h.S;
+      lo += h.S;
     }
   }
   {
@@ -729,6 +742,7 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.tiles = (const Tile *)(base + L.tiles);
   g->dev.walker_sys = (const int32_t *)(base + L.wsys);
   g->dev.fifo = (const uint32_t *)(base + L.fifo);
+  g->dev.lanes = (const uint16_t *)(base + L.lanes);
   g->dev.cells = (const uint16_t *)(base + L.cells);
   g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
   g->dev.cellrec = (const uint32_t *)(base + L.cellrec);

@@ -128,6 +128,7 @@ struct DevTables {
   const Tile *tiles;
   const int32_t *walker_sys;  // [R] system of each walker
   const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
+  const uint16_t *lanes;      // per template: sweep lane position -> template spin
   const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
   const int32_t *tile_sys;    // per 64-row tile of cell moves: its system
   const uint32_t *cellrec;    // cell records of the grid templates (see kCellRecWords)

@@ -16,9 +16,11 @@
 // with a skew that keeps the sequential order instead of an even/odd
 // reordering.
 //
-// Work split: a walker has TPW threads; thread t owns the columns
-// q = c*TPW + t, c < CPT, and visits them one after another inside a level
-// (independent attempts, so their latencies overlap).  When TPW <= 64 a
+// Work split: a walker has TPW threads; thread t owns the columns at lane
+// positions c*TPW + t, c < CPT, and visits them one after another inside a
+// level (independent attempts, so their latencies overlap).  Lane positions
+// hold the columns in order of their level offset, so the columns of a
+// wavefront start (and end) within few levels of each other.  When TPW <= 64 a
 // walker lives inside one wavefront and a level ends with a wavefront fence
 // instead of a workgroup barrier.
 //
@@ -158,9 +160,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   bool col[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int q = c * TPW + t;
-    col[c] = live && q < S;
-    const int qq0 = col[c] ? q : 0;
+    const int pos = c * TPW + t;
+    col[c] = live && pos < S;
+    const int qq0 = col[c] ? (int)T.lanes[sy.tmpl0 + pos] : 0;
     qo[c] = qq0 >> 5;
     qb[c] = qq0 & 31;
     const TmplSpin ts = T.tmpl[sy.tmpl0 + qq0];

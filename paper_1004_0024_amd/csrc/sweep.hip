@@ -84,6 +84,18 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
 
   // walker slot layout: [shadow | generator ring][queues][halo row, spins, halo row][thr][acc]
   auto wbase = [&](int w) { return lds + w * PW; };
+  // body(w, j) for every word j < per of every walker w of the tile, spread
+  // over the workgroup; a workgroup of one walker needs no division
+  auto each_word = [&](int per, auto &&body) {
+    if (nw == 1) {
+      for (int j = tid; j < per; j += nthr) body(0, j);
+    } else {
+      for (int i = tid; i < nw * per; i += nthr) {
+        const int w = i / per;
+        body(w, i - w * per);
+      }
+    }
+  };
 
   const int delta = (S - (kMtN % S)) % S;  // chunk-aligned slots
   const int kg = Zg / S;
@@ -91,34 +103,31 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   const int zs = Zg - kMtN;                // slots >= zs also live in the shadow
 
   // ---- load the walkers' state ----
-  for (int i = tid; i < nw * kMtN; i += nthr) {
-    const int w = i / kMtN, j = i - w * kMtN;
+  each_word(kMtN, [&](int w, int j) {
     const int r = sy.walker0 + tile.w0 + w;
     const uint32_t v = St.mt[(size_t)r * kMtN + j];
     uint32_t *g = wbase(w) + kMtN;
     const int x = j + delta;
     g[x] = v;
     if (x >= zs) g[x - Zg] = v;
-  }
+  });
   const int SWW = WW + 2 * RS;  // spin rows with the two halo rows
   const int TRW = TF ? T.qrow : kThrRow;  // threshold row words
   constexpr int SG = TF ? 1 : -1;         // sign of the accumulated field
   constexpr int NACC = TF ? 5 : 4;        // reduction words
-  for (int i = tid; i < nw * SWW; i += nthr) {
-    const int w = i / SWW, j = i - w * SWW;
+  each_word(SWW, [&](int w, int j) {
     int src = j - RS;  // halo rows: copies of the last and the first slice (ring), else zero
     if (src < 0) src = RING ? src + WW : -1;
     else if (src >= WW) src = RING ? src - WW : -1;
     wbase(w)[ZP + FW + j] =
         (init_mode || src < 0) ? 0u : St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + src];
-  }
+  });
   if (!init_mode) {
     const uint32_t *rows = TF ? T.qthr : T.thr;
-    for (int i = tid; i < nw * TRW; i += nthr) {
-      const int w = i / TRW, j = i - w * TRW;
+    each_word(TRW, [&](int w, int j) {
       const int slot = St.temp_of[sy.walker0 + tile.w0 + w];
       wbase(w)[ZP + FW + SWW + j] = rows[(size_t)(sy.thr0 + slot) * TRW + j];
-    }
+    });
   }
   // reduction words: running energy (the walker's cost, so a swap round in the
   // launch can read it), flips, wavefront steps, wavefront steps with a flip,
@@ -416,16 +425,19 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
   }
   __syncthreads();
-  for (int i = tid; i < nw * WW; i += nthr) {
-    const int w = i / WW, j = i - w * WW;
+  each_word(WW, [&](int w, int j) {
     St.spins[sy.spin_word0 + (size_t)(tile.w0 + w) * WW + j] = wbase(w)[ZP + FW + RS + j];
-  }
+  });
+  // the window's oldest word sits in slot (consumed + delta) mod Zg; j < kMtN < Zg,
+  // so one subtraction wraps slot + j
   const long long consumed = init_mode ? (long long)M * S : (long long)n_sweeps * M * S;
-  for (int i = tid; i < nw * kMtN; i += nthr) {
-    const int w = i / kMtN, j = i - w * kMtN;
+  const int wslot = (int)((consumed + delta) % Zg);
+  each_word(kMtN, [&](int w, int j) {
     const int r = sy.walker0 + tile.w0 + w;
-    St.mt[(size_t)r * kMtN + j] = wbase(w)[kMtN + (int)((consumed + j + delta) % Zg)];
-  }
+    int x = wslot + j;
+    if (x >= Zg) x -= Zg;
+    St.mt[(size_t)r * kMtN + j] = wbase(w)[kMtN + x];
+  });
   if (!init_mode && tid < nw) {
     const int r = sy.walker0 + tile.w0 + tid;
     const int32_t *a = (const int32_t *)(wbase(tid) + ZP + FW + SWW + TRW);

@@ -89,8 +89,10 @@ struct LadderArgs {
   int64_t sweeps0, rounds0;
 };
 // LDS words after the walker slots of a ladder workgroup: the swap stream's
-// 624-word window, walker at each slot, slot of each walker, head and count.
-constexpr int kLadderWords = kMtN + 256 + 256 + 4;
+// 624-word window, walker at each slot, slot of each walker, head and
+// near-threshold count, accepted swaps per slot, and the outcome of each pair
+// of the last round.
+constexpr int kLadderWords = kMtN + 256 + 256 + 4 + 256 + 128;
 
 // Generator ring: the 624-word look-back of MT19937 plus one chunk of S words,
 // rounded up to whole chunks.  A kMtN-word copy of its top slots sits in front

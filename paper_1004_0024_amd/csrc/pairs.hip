@@ -159,17 +159,13 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
     lds[(i >> 2) * PW + WW + kPairThrRow + (i & 3)] =
         ((i & 3) == 0 && !init_mode) ? (uint32_t)St.energy[sy.walker0 + (i >> 2)] : 0u;
   const bool ladder = la.swap_every > 0 && !init_mode;
-  uint32_t *swin = lds + K * PW;
-  int32_t *wat = (int32_t *)(swin + kMtN), *tof = wat + 256, *misc = tof + 256;
-  uint32_t *prec = swin + kLadderWords;  // template records, three arrays of S words
+  const LadderLds L = ladder_lds(lds + K * PW);
+  uint32_t *prec = lds + K * PW + kLadderWords;  // template records, three arrays of S words
   for (int q = tid; q < S; q += nthr) pair_record(T.tmpl[sy.tmpl0 + q], q, prec + q, prec + S + q, prec + 2 * S + q);
+  PairBeta pb{0.0, 0.0, 0.0};
   if (ladder) {
-    for (int j = tid; j < kMtN; j += nthr) swin[j] = St.swap_mt[(size_t)blockIdx.x * kMtN + j];
-    for (int k = tid; k < K; k += nthr) {
-      wat[k] = St.walker_at[sy.slot0 + k];
-      tof[k] = St.temp_of[sy.walker0 + k];
-    }
-    if (tid == 0) misc[0] = misc[1] = 0;
+    ladder_load(St, sy, (int)blockIdx.x, tid, nthr, L);
+    pb = pair_beta(T, sy, tid);
   }
   __syncthreads();
 
@@ -251,14 +247,19 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
       if (live && dE) atomicAdd(&acc[0], 2 * dE);
       dE = 0;
       __syncthreads();
-      if (tid == 0)
-        ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
-                          WW + kPairThrRow);
+      // a threshold row belongs to a slot: the walkers of each accepted pair trade rows
+      const int parity = (int)((la.rounds0 + n_rounds) & 1);
+      const int np = ladder_swap_round(sy, parity, tid, L, pb.lo(parity), pb.hi(parity), lds, PW, WW + kPairThrRow);
       ++n_rounds;
-      __syncthreads();
-      for (int i = tid; i < K * kPairThrRow; i += nthr) {
-        const int ww = i / kPairThrRow, j = i - ww * kPairThrRow;
-        lds[ww * PW + WW + j] = T.thr[(size_t)(sy.thr0 + tof[ww]) * kThrRow + kThrZero + j];
+      for (int i = tid; i < np * kPairThrRow; i += nthr) {
+        const int j = i / kPairThrRow, wd = i - j * kPairThrRow;
+        const int ab = L.moved[j];
+        if (ab >= 0) {
+          uint32_t *ra = lds + (ab & 0xffff) * PW + WW + wd, *rb = lds + (ab >> 16) * PW + WW + wd;
+          const uint32_t v = *ra;
+          *ra = *rb;
+          *rb = v;
+        }
       }
       __syncthreads();
     }
@@ -280,15 +281,7 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
     St.energy[r] = a[0];
     St.flips[r] += (unsigned long long)(uint32_t)a[1];
   }
-  if (ladder) {
-    const int h = misc[0];
-    for (int j = tid; j < kMtN; j += nthr) St.swap_mt[(size_t)blockIdx.x * kMtN + j] = swin[(h + j) % kMtN];
-    for (int k = tid; k < K; k += nthr) {
-      St.walker_at[sy.slot0 + k] = wat[k];
-      St.temp_of[sy.walker0 + k] = tof[k];
-    }
-    if (tid == 0 && misc[1]) atomicAdd((unsigned long long *)&St.stats[0], (unsigned long long)misc[1]);
-  }
+  if (ladder) ladder_store(St, sy, (int)blockIdx.x, tid, nthr, L, la.rounds0, n_rounds);
 }
 
 template <bool RING>

@@ -140,17 +140,14 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     if (TF && !init_mode && j == 4) v = (uint32_t)St.bond[r];
     wbase(w)[ZP + FW + SWW + TRW + j] = v;
   }
-  // ladder tiles (the whole system in this workgroup): swap state in LDS
+  // ladder tiles (the whole system in this workgroup): swap state in LDS,
+  // beta of this thread's pair in registers
   const bool ladder = LADDER && la.swap_every > 0 && !init_mode;
-  uint32_t *swin = lds + G * PW;
-  int32_t *wat = (int32_t *)(swin + kMtN), *tof = wat + 256, *misc = tof + 256;
+  const LadderLds L = ladder_lds(lds + G * PW);
+  PairBeta pb{0.0, 0.0, 0.0};
   if (ladder) {
-    for (int j = tid; j < kMtN; j += nthr) swin[j] = St.swap_mt[(size_t)tile.sys * kMtN + j];
-    for (int k = tid; k < nw; k += nthr) {
-      wat[k] = St.walker_at[sy.slot0 + k];
-      tof[k] = St.temp_of[sy.walker0 + k];
-    }
-    if (tid == 0) misc[0] = misc[1] = 0;
+    ladder_load(St, sy, tile.sys, tid, nthr, L);
+    pb = pair_beta(T, sy, tid);
   }
 
   // ---- this thread's walker and columns ----
@@ -392,19 +389,24 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         level_sync<WS>();
       }
       if (ladder && (la.sweeps0 + sw + 1) % la.swap_every == 0) {
-        // running energies up to date, one thread swaps, then every walker
-        // takes the threshold row of its (new) slot
+        // running energies up to date, then the round; a threshold row belongs
+        // to a slot, so the walkers of each accepted pair trade rows
         if (live && dE) atomicAdd(&acc[0], 2 * dE);
         dE = 0;
         __syncthreads();
-        if (tid == 0)
-          ladder_swap_round(T, St, sy, (int)((la.rounds0 + n_rounds) & 1), swin, wat, tof, misc, lds, PW,
-                            ZP + FW + SWW + TRW);
+        const int parity = (int)((la.rounds0 + n_rounds) & 1);
+        const int np = ladder_swap_round(sy, parity, tid, L, pb.lo(parity), pb.hi(parity), lds, PW,
+                                         ZP + FW + SWW + TRW);
         ++n_rounds;
-        __syncthreads();
-        for (int i = tid; i < nw * TRW; i += nthr) {
-          const int w = i / TRW, j = i - w * TRW;
-          wbase(w)[ZP + FW + SWW + j] = T.thr[(size_t)(sy.thr0 + tof[w]) * TRW + j];
+        for (int i = tid; i < np * TRW; i += nthr) {
+          const int j = i / TRW, wd = i - j * TRW;
+          const int ab = L.moved[j];
+          if (ab >= 0) {
+            uint32_t *ra = wbase(ab & 0xffff) + ZP + FW + SWW + wd, *rb = wbase(ab >> 16) + ZP + FW + SWW + wd;
+            const uint32_t v = *ra;
+            *ra = *rb;
+            *rb = v;
+          }
         }
         __syncthreads();
       }
@@ -447,15 +449,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     St.wsteps[2 * (size_t)r] += (unsigned long long)(uint32_t)a[2];
     St.wsteps[2 * (size_t)r + 1] += (unsigned long long)(uint32_t)a[3];
   }
-  if (ladder) {
-    const int h = misc[0];
-    for (int j = tid; j < kMtN; j += nthr) St.swap_mt[(size_t)tile.sys * kMtN + j] = swin[(h + j) % kMtN];
-    for (int k = tid; k < nw; k += nthr) {
-      St.walker_at[sy.slot0 + k] = wat[k];
-      St.temp_of[sy.walker0 + k] = tof[k];
-    }
-    if (tid == 0 && misc[1]) atomicAdd((unsigned long long *)&St.stats[0], (unsigned long long)misc[1]);
-  }
+  if (ladder) ladder_store(St, sy, tile.sys, tid, nthr, L, la.rounds0, n_rounds);
 }
 
 template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>

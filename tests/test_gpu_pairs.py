@@ -103,6 +103,14 @@ def test_pairs_approximate_acceptance(kind):
     _run(wl, [0, 1], [1, 7, 30], kind=kind)
 
 
+def test_pairs_long_ladder_swaps_across_wavefronts():
+    """150 walkers: a swap round has 74 or 75 pairs, so the threads that draw
+    and decide them span two wavefronts (the stream window is read by all of
+    them before any output is stored)."""
+    wl = Workload("long ladder", [make_chimera_system(2, 4, 83, 150)], 0, 1)
+    _run(wl, [0], [1, 2, 7])
+
+
 def test_pairs_config_A_long_run():
     wl = make_workload("A")
     _run(wl, [0], [1] * 5 + [995])

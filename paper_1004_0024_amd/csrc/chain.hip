@@ -103,35 +103,35 @@ __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int3
   __syncthreads();
   for (int j = tid; j < npairs; j += blockDim.x) buf[kMtN + j] = mt_next_word(buf[j], buf[j + 1], buf[j + kMtM]);
   __syncthreads();
-  if (tid == 0) {
-    unsigned long long near = 0;
-    for (int i = 0; i < npairs; ++i) {
-      const int k = p0 + 2 * i;
-      const int a = wat[k], b = wat[k + 1];
-      const int ea = St.energy[sy.walker0 + a], eb = St.energy[sy.walker0 + b];
-      double delta = (T.beta[sy.slot0 + k] - T.beta[sy.slot0 + k + 1]) * (double)(ea - eb);
-      if (T.two_field) {
-        const int ba = St.bond[sy.walker0 + a], bb = St.bond[sy.walker0 + b];
-        const double d_sp = (T.qa[sy.slot0 + k] - T.qa[sy.slot0 + k + 1]) * (double)((ea + ba) - (eb + bb));
-        const double d_t = (T.qc[sy.slot0 + k] - T.qc[sy.slot0 + k + 1]) * (double)(ba - bb);
-        delta = d_sp - d_t;
-      }
-      const uint32_t u = mt_temper(buf[kMtN + i]);
-      const double x = (double)u * 0x1p-32;
-      const double p = exp(delta);
-      const bool accept = (delta >= 0.0) || (x < p);
-      if (delta < 0.0 && fabs(x - p) < 1e-12) ++near;
-      St.swap_att[sy.slot0 + k] += 1ull;
-      if (accept) {
-        wat[k] = b;
-        wat[k + 1] = a;
-        St.temp_of[sy.walker0 + a] = k + 1;
-        St.temp_of[sy.walker0 + b] = k;
-        St.swap_acc[sy.slot0 + k] += 1ull;
-      }
+  // the round's pairs are disjoint: thread i decides pairs i, i + 64, ... with
+  // the stream outputs drawn above in pair order
+  unsigned long long near = 0;
+  for (int i = tid; i < npairs; i += blockDim.x) {
+    const int k = p0 + 2 * i;
+    const int a = wat[k], b = wat[k + 1];
+    const int ea = St.energy[sy.walker0 + a], eb = St.energy[sy.walker0 + b];
+    double delta = (T.beta[sy.slot0 + k] - T.beta[sy.slot0 + k + 1]) * (double)(ea - eb);
+    if (T.two_field) {
+      const int ba = St.bond[sy.walker0 + a], bb = St.bond[sy.walker0 + b];
+      const double d_sp = (T.qa[sy.slot0 + k] - T.qa[sy.slot0 + k + 1]) * (double)((ea + ba) - (eb + bb));
+      const double d_t = (T.qc[sy.slot0 + k] - T.qc[sy.slot0 + k + 1]) * (double)(ba - bb);
+      delta = d_sp - d_t;
     }
-    if (near) atomicAdd((unsigned long long *)&St.stats[0], near);
+    const uint32_t u = mt_temper(buf[kMtN + i]);
+    const double x = (double)u * 0x1p-32;
+    const double p = exp(delta);
+    const bool accept = (delta >= 0.0) || (x < p);
+    if (delta < 0.0 && fabs(x - p) < 1e-12) ++near;
+    St.swap_att[sy.slot0 + k] += 1ull;
+    if (accept) {
+      wat[k] = b;
+      wat[k + 1] = a;
+      St.temp_of[sy.walker0 + a] = k + 1;
+      St.temp_of[sy.walker0 + b] = k;
+      St.swap_acc[sy.slot0 + k] += 1ull;
+    }
   }
+  if (near) atomicAdd((unsigned long long *)&St.stats[0], near);
   __syncthreads();
   for (int j = tid; j < kMtN; j += blockDim.x) win[j] = buf[npairs + j];
   for (int k = tid; k < K; k += blockDim.x) {

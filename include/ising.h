@@ -203,8 +203,10 @@ void ising_replay_free(ising_replay *r);
  * chain it advances), then keep the fastest shape.  Optionally writes one row
  * {bucket, tpw, walkers_per_group, nanoseconds per sweep} per trial to
  * report[report_rows][4].  A ladder bucket only tries ladder shapes (its
- * swap rounds stay inside the kernel).  Returns the number of rows written
- * (>= 0) or an error code.  Synchronous.                                     */
+ * swap rounds stay inside the kernel); when every bucket is one, each timed
+ * launch runs 16 sweeps with a swap round after each, as ising_sweep runs
+ * them, and the report gives the time per sweep.  Returns the number of rows
+ * written (>= 0) or an error code.  Synchronous.                             */
 int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream, int64_t *report,
                        int32_t report_rows);
 

@@ -1134,6 +1134,12 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
   HIP_TRY(hipEventCreate(&e0), "autotune event");
   HIP_TRY(hipEventCreate(&e1), "autotune event");
   int32_t row = 0;
+  // When every bucket holds whole ladders, sweeps run in long launches with the
+  // swap rounds inside: time launches of 16 sweeps with a round after each,
+  // so that the per-sweep cost, not the launch's state load and store, decides.
+  const bool ladders = g->ladder_all();
+  const int32_t per = ladders ? 16 : 1;
+  const LadderArgs la = ladders ? LadderArgs{1, 0, 0, 0} : LadderArgs{0, 0, 0, 0};
   for (size_t bi = 0; bi < g->buckets.size(); ++bi) {
     int32_t Kmax = 1;
     for (int32_t sy : g->bucket_sys[bi]) Kmax = std::max(Kmax, g->sys[sy].K);
@@ -1151,14 +1157,15 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
         HIP_TRY(hipMemcpyAsync((void *)g->dev.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size(),
                                hipMemcpyHostToDevice, s),
                 "autotune tiles");
-        HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], 1, 0, s), "autotune warm-up");
+        HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], per, 0, s, la), "autotune warm-up");
         HIP_TRY(hipEventRecord(e0, s), "autotune event");
-        for (int32_t k = 0; k < reps; ++k) HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], 1, 0, s), "autotune trial");
+        for (int32_t k = 0; k < reps; ++k)
+          HIP_TRY(launch_sweep(g->dev, d, g->buckets[bi], per, 0, s, la), "autotune trial");
         HIP_TRY(hipEventRecord(e1, s), "autotune event");
         HIP_TRY(hipEventSynchronize(e1), "autotune sync");
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "autotune time");
-        const int64_t ns = (int64_t)((double)ms * 1e6 / reps);  // per sweep
+        const int64_t ns = (int64_t)((double)ms * 1e6 / ((double)reps * per));  // per sweep
         if (report && row < report_rows) {
           int64_t *o = report + (size_t)row * 4;
           o[0] = (int64_t)bi;

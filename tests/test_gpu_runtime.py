@@ -72,6 +72,32 @@ def test_autotune_keeps_the_chain():
         compare_system(st, s, ch, "after autotune")
 
 
+def test_autotune_ladder_graph_keeps_the_chain():
+    """A graph whose buckets all hold whole ladders is tuned on 16-sweep launches
+    with the swap rounds inside the kernel: the tuned shapes stay ladder shapes,
+    the fastest trial is kept, and the chain (swaps in the kernel, cadences 1
+    and 2) is the oracle's."""
+    import paper_1004_0024_amd as pa
+    wl = Workload("tune ladders", [make_chimera_system(2, 8, 53, 16), make_chimera_system(2, 5, 54, 12)], 0, 1)
+    say("autotune", wl.name)
+    g = pa.Graph(wl.systems)
+    assert all(b["ladder"] == 1 for b in g.buckets())
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    rows = g.autotune(scratch, reps=2)
+    assert len(rows) >= 2 and all(r["ns_per_sweep"] > 0 for r in rows)
+    assert all(b["ladder"] == 1 for b in g.buckets())
+    for bi, b in enumerate(g.buckets()):
+        best = min((r for r in rows if r["bucket"] == bi), key=lambda r: r["ns_per_sweep"])
+        assert (b["tpw"], b["G"]) == (best["tpw"], best["G"])
+    st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    chains = chains_for(wl, [0, 1])
+    for n, every in ((7, 1), (6, 2)):
+        st.sweep(n, every)
+        for s, ch in enumerate(chains):
+            ch.sweeps(n, every)
+            compare_system(st, s, ch, f"after ladder autotune, {n} sweeps, swap every {every}")
+
+
 def test_checkpoint_resume_bit_identical():
     """Saving every state buffer and the two counters, then resuming, continues
     the chain exactly as an uninterrupted run."""

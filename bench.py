@@ -63,10 +63,21 @@ def cpu_baseline(wl, budget_s=20.0):
     t0 = time.perf_counter()
     oracle.run_many(chains, n, 1, ncores)
     dt = time.perf_counter() - t0
+    # one thread on the first system, a per-core figure (the paper quotes per-core rates)
+    one = oracle.workload_chains(wl, [0])
+    t0 = time.perf_counter()
+    oracle.run_many(one, 1, 1, 1)
+    t1c = time.perf_counter() - t0
+    n1 = max(1, min(int(3.0 / max(t1c, 1e-3)), wl.n_sweeps - 2))
+    t0 = time.perf_counter()
+    oracle.run_many(one, n1, 1, 1)
+    d1 = time.perf_counter() - t0
     return {"value": per_sweep * n / dt, "unit": "spin-flip attempts/s", "cores": int(min(ncores, nsys)),
             "kind": "oracle",
             "sample": f"{nsys} of {len(wl.systems)} systems x {wl.systems[0].K} walkers x {n} sweeps "
-                      f"(swap every sweep), {dt:.1f} s"}
+                      f"(swap every sweep), {dt:.1f} s",
+            "one_core": {"value": wl.systems[0].N * wl.systems[0].K * n1 / d1,
+                         "sample": f"1 system x {wl.systems[0].K} walkers x {n1} sweeps, 1 thread, {d1:.1f} s"}}
 
 
 def batch_leg(name, n_sweeps, reps=3):

@@ -241,6 +241,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   // front included), so only the words with o < S are computed and stored.
   auto gen_chunk = [&](int gslot, int chunk) {
     if (!live) return;
+    // the generating wavefronts set the pace of the level's barrier: they
+    // issue first while they generate (wave priority, back to 0 after)
+    __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int h = 0; h < CPT; ++h) {
       const int j = t + h * TPW;
@@ -265,6 +268,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
   };
   auto advance = [Zg, S](int x) {
     x += S;

@@ -29,7 +29,7 @@ LANE_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
 # HBM bytes per sweep launch on the throughput workload, from rocprofv3 FETCH_SIZE (x2.00) and
 # WRITE_SIZE (x1.00) scaled against a device copy of known size (sweep kernel unchanged since).
-SWEEP_TRAFFIC_BYTES = {"B": 161.4e6}
+SWEEP_TRAFFIC_BYTES = {"B": 161.5e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
 
 

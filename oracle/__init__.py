@@ -1,7 +1,7 @@
 """Oracle -- TEST INFRASTRUCTURE ONLY.
 
-Python wrapper over the plain C oracle in ``orc.c`` (and the learned-proposal
-oracle in ``mlp.py``).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+Python wrapper over the plain C oracle in ``orc.c``; the learned-proposal
+oracle is ``learned.py`` and the cell heat-bath oracle ``heatbath.py``.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
 code with the HIP library under ``paper_1004_0024_amd/``.
 """
@@ -213,9 +213,9 @@ class Chain:
         f = np.empty(self.K, np.uint64)
         a = np.empty(self.K, np.uint64)
         c = np.empty(self.K, np.uint64)
-        n = np.zeros(1, np.uint64)
+        n = np.empty(self.K, np.uint64)
         lib().orc_get_counters(self._c, _ptr(f), _ptr(a), _ptr(c), _ptr(n))
-        return {"flips": f, "swap_att": a, "swap_acc": c, "near": int(n[0])}
+        return {"flips": f, "swap_att": a, "swap_acc": c, "swap_near": n, "near": int(n.sum())}
 
     def energy_of(self, w):
         return int(lib().orc_energy_of(self._c, w))

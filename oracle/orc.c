@@ -88,7 +88,7 @@ struct orc_chain {
   orc_mt *mt;
   orc_mt swap;
   int32_t *temp_of, *walker_at;
-  uint64_t *flips, *sw_att, *sw_acc, near;
+  uint64_t *flips, *sw_att, *sw_acc, *sw_near; /* per pair (k, k+1), at slot k */
   int64_t sweeps, rounds;
   int32_t accept_kind; /* ORC_ACCEPT_EXACT / _FAST / _ACCURATE */
   int32_t *ce;         /* input edge of each adjacency entry */
@@ -191,6 +191,7 @@ orc_chain *orc_new(int32_t N, int32_t nE, const int32_t *u, const int32_t *v, co
   c->flips = (uint64_t *)calloc((size_t)K, sizeof(uint64_t));
   c->sw_att = (uint64_t *)calloc((size_t)K, sizeof(uint64_t));
   c->sw_acc = (uint64_t *)calloc((size_t)K, sizeof(uint64_t));
+  c->sw_near = (uint64_t *)calloc((size_t)K, sizeof(uint64_t));
   for (int32_t w = 0; w < K; w++) {
     orc_mt_seed(&c->mt[w], walker_seed[w]);
     /* initial spin i: +1 when the top bit of the walker's i-th output is set */
@@ -219,6 +220,7 @@ void orc_free(orc_chain *c) {
   free(c->flips);
   free(c->sw_att);
   free(c->sw_acc);
+  free(c->sw_near);
   free(c->ce);
   free(c->ctau);
   free(c->htau);
@@ -468,7 +470,7 @@ void orc_swap_round(orc_chain *c, int32_t parity) {
     double uniform = (double)u * 0x1p-32;
     double p = exp(delta);
     int accept = (delta >= 0.0) || (uniform < p);
-    if (delta < 0.0 && fabs(uniform - p) < 1e-12) c->near++;
+    if (delta < 0.0 && fabs(uniform - p) < 1e-12) c->sw_near[k]++; /* decided within 1e-12 */
     c->sw_att[k]++;
     if (accept) {
       c->walker_at[k] = b;
@@ -559,11 +561,11 @@ void orc_get_swap_mt(const orc_chain *c, uint32_t *win624, int64_t *used) {
   *used = c->swap.n;
 }
 void orc_get_counters(const orc_chain *c, uint64_t *flips, uint64_t *sw_att, uint64_t *sw_acc,
-                      uint64_t *near_threshold) {
+                      uint64_t *sw_near) {
   memcpy(flips, c->flips, sizeof(uint64_t) * (size_t)c->K);
   memcpy(sw_att, c->sw_att, sizeof(uint64_t) * (size_t)c->K);
   memcpy(sw_acc, c->sw_acc, sizeof(uint64_t) * (size_t)c->K);
-  *near_threshold = c->near;
+  memcpy(sw_near, c->sw_near, sizeof(uint64_t) * (size_t)c->K);
 }
 
 int64_t orc_check_fields(const orc_chain *c) {

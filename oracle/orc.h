@@ -69,8 +69,10 @@ void orc_get_energy(const orc_chain *c, int64_t *out); /* [K] running energy */
 void orc_get_labels(const orc_chain *c, int32_t *temp_of, int32_t *walker_at);
 void orc_get_mt(const orc_chain *c, uint32_t *win /*[K][624]*/, int64_t *used /*[K]*/);
 void orc_get_swap_mt(const orc_chain *c, uint32_t *win624, int64_t *used);
+/* Per walker: accepted flips.  Per pair (k, k+1), at index k: swap attempts,
+ * acceptances, and decisions with |u 2^-32 - exp(Delta)| < 1e-12 (Delta < 0). */
 void orc_get_counters(const orc_chain *c, uint64_t *flips /*[K]*/, uint64_t *sw_att /*[K]*/,
-                      uint64_t *sw_acc /*[K]*/, uint64_t *near_threshold);
+                      uint64_t *sw_acc /*[K]*/, uint64_t *sw_near /*[K]*/);
 /* Energy of walker w's spins by the cost function itself. */
 int64_t orc_energy_of(const orc_chain *c, int32_t w);
 /* Number of running fields / energies that differ from a recomputation. */

@@ -259,6 +259,30 @@ def pin_labels_consistent():
         assert all(t[w[k]] == k for k in range(7))
 
 
+def pin_near_threshold_swaps():
+    """Constructed decisions with exp(Delta) - u 2^-32 = +-1e-14 are counted once, on their
+    pair, and decided as the exact comparison decides them; at 3e-12 they are not counted.
+    The count is taken on the initial energies and after a sweep."""
+    from . import near_case
+    for offset, counted in ((1e-14, 1), (-1e-14, 1), (3e-12, 0), (-3e-12, 0)):
+        for after in (False, True):
+            nc = near_case.build(offset, after)
+            assert (nc.gap > 0) == (offset > 0) and 0.5 * abs(offset) < abs(nc.gap) < 2 * abs(offset)
+            ch = oracle.workload_chains(nc.workload)[0]
+            if after:
+                ch.sweeps(1, swap_every=1)
+            else:
+                ch.swap_round(0)
+            c = ch.counters()
+            assert list(c["swap_near"]) == [counted, 0, 0], (offset, after, c["swap_near"])
+            assert list(c["swap_att"]) == [1, 0, 0]
+            assert int(c["swap_acc"][0]) == int(nc.accept), (offset, after)
+            t, w = ch.labels()
+            assert list(w) == ([1, 0, 2] if nc.accept else [0, 1, 2])
+            sw, used = ch.swap_mt()
+            assert used == 1
+
+
 ALL_PINS = [
     pin_mt_known_answer,
     pin_mt_matches_library,
@@ -275,4 +299,5 @@ ALL_PINS = [
     pin_swap_schedule_and_draws,
     pin_labels_consistent,
     pin_initial_spins_reading,
+    pin_near_threshold_swaps,
 ]

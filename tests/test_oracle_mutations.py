@@ -34,6 +34,11 @@ MUTATIONS = [
     ("mt_seed_mult", "1812433253u", "1812433257u"),
     ("energy_field_sign", "e -= (int64_t)c->h[i] * s[i];", "e += (int64_t)c->h[i] * s[i];"),
     ("init_bit", "(orc_mt_next(&c->mt[w]) >> 31) ? 1 : -1", "(orc_mt_next(&c->mt[w]) & 1u) ? 1 : -1"),
+    ("near_width_narrow", "fabs(uniform - p) < 1e-12) c->sw_near[k]++;", "fabs(uniform - p) < 1e-15) c->sw_near[k]++;"),
+    ("near_width_wide", "fabs(uniform - p) < 1e-12) c->sw_near[k]++;", "fabs(uniform - p) < 1e-11) c->sw_near[k]++;"),
+    ("near_wrong_pair", "fabs(uniform - p) < 1e-12) c->sw_near[k]++;", "fabs(uniform - p) < 1e-12) c->sw_near[k + 1]++;"),
+    ("near_only_rejected", "if (delta < 0.0 && fabs(uniform - p) < 1e-12)", "if (delta < 0.0 && !accept && fabs(uniform - p) < 1e-12)"),
+    ("swap_accept_le", "int accept = (delta >= 0.0) || (uniform < p);", "int accept = (delta >= 0.0) || (uniform <= p + 1e-13);"),
 ]
 
 RUNNER = r"""

@@ -11,8 +11,10 @@ line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,10 +29,37 @@ BYTES_PER_ATTEMPT = 12         # spin r+w 2 B, field r+w 2 B, MT word r+w 8 B
 LANE_OPS_PER_ATTEMPT = 60
 LANE_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
-# HBM bytes per sweep launch on the throughput workload, from rocprofv3 FETCH_SIZE (x2.00) and
-# WRITE_SIZE (x1.00) scaled against a device copy of known size (sweep kernel unchanged since).
-SWEEP_TRAFFIC_BYTES = {"B": 161.5e6}
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
+# Measured HBM traffic and VALU issue of the sweep kernel come from the committed rocprofv3 summary
+# of the workload (a "measured:" JSON line in profiles/sweep_kernel_<config>_counters.md), and are
+# reported only while the kernel's sources hash to the value recorded there.
+SWEEP_SOURCES = ["sweep.hip", "internal.h", "mt19937.h", "swap_round.h"]
+
+
+def sweep_sources_hash():
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1004_0024_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_counters(config):
+    """(figures, why): the profile's measured line when its source hash matches, else None."""
+    path = os.path.join("profiles", f"sweep_kernel_{config}_counters.md")
+    try:
+        text = open(os.path.join(ROOT, path)).read()
+    except OSError:
+        return None, f"no {path}"
+    m = re.search(r"^measured: (\{.*\})\s*$", text, re.M)
+    if not m:
+        return None, f"{path} has no measured line"
+    fig = json.loads(m.group(1))
+    now = sweep_sources_hash()
+    if fig.get("sources_sha256") != now:
+        return None, f"stale: {path} was taken with sweep sources {fig.get('sources_sha256')}, now {now}"
+    fig["source"] = path
+    return fig, None
 
 
 def alu_roofline(attempts_per_s):
@@ -80,6 +109,37 @@ def cpu_baseline(wl, budget_s=20.0):
                          "sample": f"1 system x {wl.systems[0].K} walkers x {n1} sweeps, 1 thread, {d1:.1f} s"}}
 
 
+def progress(*a):
+    """A line on stderr when a leg ends (the JSON line is the only stdout output)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def tuned_graph(wl, reps=3):
+    """The workload's graph with the launch shapes the autotuner picks (timed on a
+    scratch state), as every timed leg here uses it; the parity tests call this
+    too, so they run the shapes that are timed."""
+    import paper_1004_0024_amd as pa
+
+    g = pa.Graph(wl.systems)
+    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
+    trials = g.autotune(scratch, reps=reps)
+    del scratch
+    return g, trials
+
+
+def throughput_step(st, n_sweeps, stream=None, evs=None):
+    """One timed step of the throughput workload: n_sweeps single-sweep launches,
+    each followed by a swap round (round t tries the pairs of parity t mod 2; the
+    step starts at an even round count); evs, if given, time every sweep launch."""
+    for t in range(n_sweeps):
+        if evs is not None:
+            evs[2 * t].record(stream)
+        st.sweep(1, 0)
+        if evs is not None:
+            evs[2 * t + 1].record(stream)
+        st.swap(t & 1)
+
+
 def batch_leg(name, n_sweeps, reps=3):
     """Attempts/s of another workload shape: the launch shapes autotuned, then one
     captured loop of `n_sweeps` sweeps (each followed by a swap round) replayed
@@ -90,10 +150,7 @@ def batch_leg(name, n_sweeps, reps=3):
     from gen import make_workload
 
     wl = make_workload(name)
-    g = pa.Graph(wl.systems)
-    scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
-    g.autotune(scratch, reps=2)
-    del scratch
+    g, _ = tuned_graph(wl, reps=2)
     st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
     rep = st.capture(n_sweeps, swap_every=1)
     rep.launch()
@@ -105,11 +162,17 @@ def batch_leg(name, n_sweeps, reps=3):
     e1.record(rep.stream)
     rep.stream.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    rate = g.attempts_per_sweep * n_sweeps / (ms / 1e3)
+    achieved = BYTES_PER_ATTEMPT * rate / 1e9
     return {"workload": wl.name, "systems": len(wl.systems), "walkers": g.R,
             "attempts_per_sweep": g.attempts_per_sweep, "sweeps_per_replay": n_sweeps,
             "buckets": len(g.buckets()), "ms_per_sweep": ms / n_sweeps,
             "launch_shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")} for b in g.buckets()],
-            "value": g.attempts_per_sweep * n_sweeps / (ms / 1e3), "unit": "spin-flip attempts/s"}
+            "value": rate, "unit": "spin-flip attempts/s",
+            # the whole replay (sweep kernels, swap rounds, side-stream joins) against the 12 B model
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_attempt": BYTES_PER_ATTEMPT,
+                         "alu": alu_roofline(rate)}}
 
 
 def two_field_leg(steps, gamma=1.0):
@@ -350,14 +413,13 @@ def main():
     from gen import make_workload
 
     wl = make_workload(args.config)
-    g = pa.Graph(wl.systems)
     tuned = None
     if not args.no_autotune:
-        scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
-        trials = g.autotune(scratch, reps=3)
-        del scratch
+        g, trials = tuned_graph(wl, reps=3)
         tuned = {"trials": len(trials), "shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")}
                                                    for b in g.buckets()]}
+    else:
+        g = pa.Graph(wl.systems)
     st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
     if args.copy_mib:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -369,13 +431,7 @@ def main():
     n_sw = wl.n_sweeps
 
     def one_step(evs=None):
-        for t in range(n_sw):
-            if evs is not None:
-                evs[2 * t].record(stream)
-            st.sweep(1, 0)
-            if evs is not None:
-                evs[2 * t + 1].record(stream)
-            st.swap(t & 1)
+        throughput_step(st, n_sw, stream, evs)
 
     for _ in range(args.warmup):
         one_step()
@@ -430,7 +486,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": SWEEP_TRAFFIC_BYTES.get(args.config), "traffic_unit": "HBM bytes per launch",
+                     "model": "algorithmic: 12 B per attempt (spin r+w 2, field r+w 2, MT word r+w 8) x "
+                              "attempts per launch / live mean launch time; the kernel keeps its state in "
+                              "LDS and moves far fewer bytes (traffic, measured)",
+                     "traffic": None, "traffic_unit": "HBM bytes per launch",
                      "kernel": "sweep_kernel", "kernel_avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_attempt": BYTES_PER_ATTEMPT,
                      "alu": alu_roofline(g.attempts_per_sweep / avg_sweep_s)},
@@ -442,19 +501,39 @@ def main():
         # flipped (the analogue of the paper's probability of waiting for a flip)
         "flip_rate": stats["flips"] / max(1, stats["attempts"]),
         "wave_steps_with_flip": stats["wave_flip_steps"] / max(1, stats["wave_steps"]),
+        # FP64 swap decisions within 1e-12 of their threshold, over every round of this run
+        "near_threshold": {"count": stats["near"], "swap_decisions": stats["swap_att"]},
     }
+    fig, why = measured_counters(args.config)
+    if fig is not None:
+        out["roofline"]["traffic"] = fig["hbm_bytes_per_launch"]
+        out["roofline"]["measured"] = {
+            "source": fig["source"], "sources_sha256": fig["sources_sha256"],
+            "hbm_GBs": fig["hbm_bytes_per_launch"] / avg_sweep_s / 1e9,
+            "hbm_frac": fig["hbm_bytes_per_launch"] / avg_sweep_s / 1e9 / HBM_PEAK_GBS,
+            "valu_busy": fig.get("valu_busy"), "valu_per_64_attempts": fig.get("valu_per_64_attempts")}
+    else:
+        out["roofline"]["traffic_note"] = why
     del rep, st
+    progress("throughput workload", f"{value:.4g} attempts/s")
     if not args.no_batches:
-        out["other_shapes"] = [batch_leg("A", 1000), batch_leg("C", 20), batch_leg("D", 10)]
+        out["other_shapes"] = []
+        for name, n, reps in (("A", 1000, 3), ("C", 200, 3), ("D", 1000, 2)):
+            out["other_shapes"].append(batch_leg(name, n, reps))
+            progress("workload", name, f"{out['other_shapes'][-1]['value']:.4g} attempts/s")
     if not args.no_two_field:
         out["two_field"] = two_field_leg(max(2, args.steps // 2))
         out["two_field"]["over_one_field"] = out["two_field"]["value"] / value
+        progress("two-field form done")
     if not args.no_pairs:
         out["layer_pairs"] = [pairs_leg("B", 100, max(2, args.steps // 2)), pairs_leg("A", 1000, 3)]
+        progress("layer-pair order done")
     if not args.no_learned:
         out["effective_samples"] = learned_leg(args.ess_steps)
+        progress("learned proposal done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

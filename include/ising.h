@@ -36,7 +36,8 @@
  *     system's swap stream per pair, accepted iff delta >= 0 or
  *     u * 2^-32 < exp(delta), delta = (beta_k - beta_k+1) * (E_a - E_b) in
  *     IEEE double, a / b the walkers at slots k / k+1.  Decisions with
- *     |u * 2^-32 - exp(delta)| < 1e-12 are counted (stats[ISING_STAT_NEAR]).
+ *     |u * 2^-32 - exp(delta)| < 1e-12 are counted per pair (swap_near) and in
+ *     total (stats[ISING_STAT_NEAR]).
  *
  * Ownership: every device buffer belongs to the caller (e.g. torch tensors);
  * the library never allocates device memory.  Host arrays passed in are read
@@ -149,12 +150,15 @@ typedef struct {
   uint64_t *wsteps;    /* [R][2] per walker: wavefront steps with an active spin, with a flip */
   int32_t *bond;       /* [R] tau-bond sum B = sum over tau edges of J_tau s s' (kept current by
                           ising_init_state, ising_refresh_energies and two-field sweeps) */
+  uint64_t *swap_near; /* [slots] decisions of pair (k, k+1), at slot index k, taken with
+                          |u 2^-32 - exp(delta)| < 1e-12 (delta < 0): the FP64 step's
+                          near-threshold count, per pair */
   int64_t sweeps;      /* host: sweeps done (set by the library) */
   int64_t rounds;      /* host: swap rounds done */
 } ising_state;
 
 enum {
-  ISING_STAT_NEAR = 0,       /* swap decisions within 1e-12 of the threshold */
+  ISING_STAT_NEAR = 0,       /* swap decisions within 1e-12 of the threshold (sum of swap_near) */
   ISING_STAT_WAVE_STEPS = 1, /* wavefront steps (64 lanes, one level) with an active spin */
   ISING_STAT_WAVE_FLIP = 2,  /* of those, steps in which some lane flipped (the analogue of
                                 the paper's probability of waiting for a flip, Section 4) */
@@ -166,8 +170,8 @@ enum {
 };
 
 /* Element counts: [spins, mt, energy, temp_of, walker_at, swap_mt, flips,
- * swap_att, swap_acc, stats, wsteps, bond]. */
-#define ISING_STATE_NARRAYS 12
+ * swap_att, swap_acc, stats, wsteps, bond, swap_near]. */
+#define ISING_STATE_NARRAYS 13
 int32_t ising_state_sizes(const ising_graph *g, int64_t *counts);
 
 /* Seed every walker stream (MT19937 init_genrand with walker_seeds[r]) and
@@ -386,7 +390,12 @@ int32_t ising_heatbath_cells(const ising_graph *g, ising_state *st, uint64_t key
 /* ---- host-only helpers (no device work; usable without a GPU) ------------ */
 
 /* thr[d] = ceil(2^32 * exp(-2.0 * beta * d)) - 1 for d = 1..dmax, thr[0] =
- * 0xffffffff: a flip with d <= 0 or u <= thr[d] is accepted.                */
+ * 0xffffffff: a flip with d <= 0 or u <= thr[d] is accepted.  ISING_E_RANGE
+ * when 2 beta dmax > 700: there exp(-2 beta d) leaves the normal doubles and
+ * no uint32 threshold expresses "never" (the same bound as the two-field
+ * rows).  ising_load_graph applies it with each system's own largest
+ * |h_i| + sum_j |J_ij|, so a ladder whose coldest beta exceeds
+ * 350 / that bound is rejected.                                              */
 int32_t ising_threshold_row(double beta, int32_t dmax, uint32_t *thr);
 /* Level offsets of the exact parallel schedule of one template: f[q] is the
  * length of the longest chain of in-slice edges leading to q in ascending

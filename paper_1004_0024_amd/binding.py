@@ -34,7 +34,7 @@ class StateStruct(C.Structure):
         ("spins", C.c_void_p), ("mt", C.c_void_p), ("energy", C.c_void_p), ("temp_of", C.c_void_p),
         ("walker_at", C.c_void_p), ("swap_mt", C.c_void_p), ("flips", C.c_void_p),
         ("swap_att", C.c_void_p), ("swap_acc", C.c_void_p), ("stats", C.c_void_p), ("wsteps", C.c_void_p),
-        ("bond", C.c_void_p), ("sweeps", C.c_int64), ("rounds", C.c_int64),
+        ("bond", C.c_void_p), ("swap_near", C.c_void_p), ("sweeps", C.c_int64), ("rounds", C.c_int64),
     ]
 
 
@@ -248,7 +248,7 @@ class State:
     """Chain state in torch device tensors, walker-major."""
 
     _FIELDS = ["spins", "mt", "energy", "temp_of", "walker_at", "swap_mt", "flips", "swap_att", "swap_acc",
-               "stats", "wsteps", "bond"]
+               "stats", "wsteps", "bond", "swap_near"]
 
     def __init__(self, graph: Graph):
         import torch
@@ -258,7 +258,8 @@ class State:
         dev = graph.tables.device
         dt = {"spins": torch.int32, "mt": torch.int32, "energy": torch.int32, "temp_of": torch.int32,
               "walker_at": torch.int32, "swap_mt": torch.int32, "flips": torch.int64, "swap_att": torch.int64,
-              "swap_acc": torch.int64, "stats": torch.int64, "wsteps": torch.int64, "bond": torch.int32}
+              "swap_acc": torch.int64, "stats": torch.int64, "wsteps": torch.int64, "bond": torch.int32,
+              "swap_near": torch.int64}
         self.t = {}
         for name, n in zip(self._FIELDS, counts):
             self.t[name] = torch.zeros(max(int(n), 1), dtype=dt[name], device=dev)

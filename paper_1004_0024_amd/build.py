@@ -1,4 +1,5 @@
-"""Build libising.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libising.so (HIP, gfx950) in-tree: kernels and device-side ABI with hipcc,
+the host-only planning code (csrc/*.cpp) with the host C++ compiler."""
 from __future__ import annotations
 
 import glob
@@ -10,6 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libising.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
+ROCM_INCLUDE = "/opt/rocm/include"
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -19,17 +22,28 @@ FLAGS = [
 ]
 
 
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE,
+              "-Wall", "-Wno-unused-function"]
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def host_sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def build(verbose: bool = False) -> str:
     """Compile every source (one hipcc process each, side by side) and link."""
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     jobs = []
-    for src in sources():
+    for src in sources() + host_sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd = [CXX, *HOST_FLAGS, "-c", src, "-o", obj]
+        else:
+            cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

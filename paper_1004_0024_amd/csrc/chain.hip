@@ -25,11 +25,12 @@ hipError_t launch_seed(const DevState &s, int32_t R, int32_t n_sys, hipStream_t 
 }
 
 // ---- totals of the per-walker and per-pair counters -----------------------
-// stats[1..2] wavefront steps, [4] flips, [5..6] swap attempts / acceptances;
-// one workgroup, fixed-order tree reductions (no atomics).
+// stats[0] near-threshold swaps, [1..2] wavefront steps, [4] flips, [5..6]
+// swap attempts / acceptances; one workgroup, fixed-order tree reductions (no
+// atomics).
 __global__ void __launch_bounds__(256) reduce_stats_kernel(DevState St, int32_t R, int32_t slots) {
-  __shared__ unsigned long long red[5][256];
-  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  __shared__ unsigned long long red[6][256];
+  unsigned long long v[6] = {0, 0, 0, 0, 0, 0};
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     v[0] += St.wsteps[2 * (size_t)r];
     v[1] += St.wsteps[2 * (size_t)r + 1];
@@ -38,15 +39,17 @@ __global__ void __launch_bounds__(256) reduce_stats_kernel(DevState St, int32_t 
   for (int k = threadIdx.x; k < slots; k += blockDim.x) {
     v[3] += St.swap_att[k];
     v[4] += St.swap_acc[k];
+    v[5] += St.swap_near[k];
   }
-  for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = v[i];
+  for (int i = 0; i < 6; ++i) red[i][threadIdx.x] = v[i];
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+      for (int i = 0; i < 6; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    St.stats[0] = red[5][0];
     St.stats[1] = red[0][0];
     St.stats[2] = red[1][0];
     St.stats[4] = red[2][0];
@@ -105,7 +108,6 @@ __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int3
   __syncthreads();
   // the round's pairs are disjoint: thread i decides pairs i, i + 64, ... with
   // the stream outputs drawn above in pair order
-  unsigned long long near = 0;
   for (int i = tid; i < npairs; i += blockDim.x) {
     const int k = p0 + 2 * i;
     const int a = wat[k], b = wat[k + 1];
@@ -121,7 +123,7 @@ __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int3
     const double x = (double)u * 0x1p-32;
     const double p = exp(delta);
     const bool accept = (delta >= 0.0) || (x < p);
-    if (delta < 0.0 && fabs(x - p) < 1e-12) ++near;
+    if (delta < 0.0 && fabs(x - p) < 1e-12) St.swap_near[sy.slot0 + k] += 1ull;
     St.swap_att[sy.slot0 + k] += 1ull;
     if (accept) {
       wat[k] = b;
@@ -131,7 +133,6 @@ __global__ void __launch_bounds__(64) swap_kernel(DevTables T, DevState St, int3
       St.swap_acc[sy.slot0 + k] += 1ull;
     }
   }
-  if (near) atomicAdd((unsigned long long *)&St.stats[0], near);
   __syncthreads();
   for (int j = tid; j < kMtN; j += blockDim.x) win[j] = buf[npairs + j];
   for (int k = tid; k < K; k += blockDim.x) {

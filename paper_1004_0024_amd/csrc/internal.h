@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace ising {
 
 constexpr int kMtN = 624;       // MT19937 words
@@ -89,9 +91,9 @@ struct LadderArgs {
   int64_t sweeps0, rounds0;
 };
 // LDS words after the walker slots of a ladder workgroup: the swap stream's
-// 624-word window, walker at each slot, slot of each walker, head and
-// near-threshold count, accepted swaps per slot, and the outcome of each pair
-// of the last round.
+// 624-word window, walker at each slot, slot of each walker, the window's head
+// (and 3 spare words), accepted swaps per slot, and the outcome of each pair of
+// the last round.
 constexpr int kLadderWords = kMtN + 256 + 256 + 4 + 256 + 128;
 
 // Generator ring: the 624-word look-back of MT19937 plus one chunk of S words,
@@ -147,7 +149,23 @@ struct DevState {
   uint32_t *swap_mt;
   uint64_t *flips, *swap_att, *swap_acc, *stats, *wsteps;
   int32_t *bond;  // running sum over tau edges of J_tau s s' (two-field form)
+  uint64_t *swap_near;  // per pair (k, k+1), at slot k: swap decisions within 1e-12 of the threshold
 };
+
+// Raise the dynamic LDS limit of `kern` to `bytes`, once per device: bit d of
+// `done` records device d (the attribute is set with that device current).
+// Setting it is idempotent, so two threads racing here both just set it.
+template <typename Kern>
+inline hipError_t allow_lds(Kern kern, int bytes, std::atomic<uint64_t> &done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = 1ull << (dev & 63);
+  if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+  e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
 
 // Kernel launchers (each returns the hipError_t of the launch).
 // Expand the seed stored in word 0 of every walker / swap stream window into

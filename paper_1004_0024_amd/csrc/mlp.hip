@@ -383,13 +383,9 @@ int mlp_grad_parts(int32_t n) { return std::max(1, std::min(kMlpParts, (n + 31) 
 
 hipError_t launch_mlp_grad(const float *w, const uint16_t *wb, const float *x, const uint8_t *y, int32_t n,
                            float *part, float *grad, float *loss, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)sizeof(GradLds));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e = allow_lds(mlp_grad_kernel, (int)sizeof(GradLds), attr);
+  if (e != hipSuccess) return e;
   const int P = mlp_grad_parts(n);
   hipLaunchKernelGGL(mlp_grad_kernel, dim3(P), dim3(256), sizeof(GradLds), st, w, wb, x, y, n, part);
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kNParams + 1 + 63) / 64), dim3(256), 0, st, part, P, n, grad, loss);

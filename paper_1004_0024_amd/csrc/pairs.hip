@@ -249,7 +249,8 @@ __global__ void __launch_bounds__(1024) pairs_kernel(DevTables T, DevState St, u
       __syncthreads();
       // a threshold row belongs to a slot: the walkers of each accepted pair trade rows
       const int parity = (int)((la.rounds0 + n_rounds) & 1);
-      const int np = ladder_swap_round(sy, parity, tid, L, pb.lo(parity), pb.hi(parity), lds, PW, WW + kPairThrRow);
+      const int np = ladder_swap_round(sy, parity, tid, L, pb.lo(parity), pb.hi(parity), lds, PW, WW + kPairThrRow,
+                                       (unsigned long long *)St.swap_near + sy.slot0);
       ++n_rounds;
       for (int i = tid; i < np * kPairThrRow; i += nthr) {
         const int j = i / kPairThrRow, wd = i - j * kPairThrRow;
@@ -289,11 +290,10 @@ static hipError_t launch_pairs_variant(const DevTables &t, const DevState &s, ui
                                        int32_t n_sys, int32_t threads, size_t lds, int32_t n_sweeps,
                                        int32_t init_mode, LadderArgs la, hipStream_t st) {
   auto kern = pairs_kernel<RING>;
-  static bool lds_limit_set = false;
-  if (!lds_limit_set && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  static std::atomic<uint64_t> lds_limit_set{0};
+  if (lds > 64 * 1024) {
+    hipError_t e = allow_lds(kern, 160 * 1024, lds_limit_set);
     if (e != hipSuccess) return e;
-    lds_limit_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(n_sys), dim3(threads), lds, st, t, s, pmt, n_lanes, n_sweeps, init_mode, la);
   return hipGetLastError();

@@ -9,9 +9,8 @@ namespace ising {
 
 // The swap state in LDS (kLadderWords words): the swap stream's circular
 // 624-word window with its head in misc[0], the walker at each slot and the
-// slot of each walker, the near-threshold count in misc[1], accepted swaps per
-// slot in this launch, and per pair of the last round a | b << 16 when the
-// walkers a and b traded slots, else -1.
+// slot of each walker, accepted swaps per slot in this launch, and per pair of
+// the last round a | b << 16 when the walkers a and b traded slots, else -1.
 struct LadderLds {
   uint32_t *swin;
   int32_t *wat, *tof, *misc;
@@ -37,9 +36,13 @@ static __device__ __forceinline__ LadderLds ladder_lds(uint32_t *base) {
 // never depend on one another, so thread j computes output j from the window
 // as it stood before the round.  bk and bk1 are beta of slots k and k + 1 of
 // the calling thread's pair; wslots + w * PW + acc_off holds walker w's
-// running cost.  Returns the number of pairs.
+// running cost.  A decision within 1e-12 of its threshold is counted in
+// near[k], the system's row of the per-pair counts (for a given parity thread
+// j always takes the same k, so no other thread writes that entry).  Returns
+// the number of pairs.
 static __device__ int ladder_swap_round(const SysInfo &sy, int parity, int tid, const LadderLds &L, double bk,
-                                        double bk1, const uint32_t *wslots, int PW, int acc_off) {
+                                        double bk1, const uint32_t *wslots, int PW, int acc_off,
+                                        unsigned long long *near) {
 #pragma clang fp contract(off)
   const int K = sy.K, p0 = parity & 1, np = (K - p0) / 2;
   const int h = L.misc[0];
@@ -61,7 +64,7 @@ static __device__ int ladder_swap_round(const SysInfo &sy, int parity, int tid, 
     const double xu = (double)mt_temper(x) * 0x1p-32;
     const double p = exp(delta);
     const bool accept = (delta >= 0.0) || (xu < p);
-    if (delta < 0.0 && fabs(xu - p) < 1e-12) atomicAdd(&L.misc[1], 1);
+    if (delta < 0.0 && fabs(xu - p) < 1e-12) near[k] += 1ull;
     L.moved[tid] = accept ? (a | (b << 16)) : -1;
     if (accept) {
       L.wat[k] = b;
@@ -104,13 +107,12 @@ static __device__ void ladder_load(const DevState &St, const SysInfo &sy, int sy
     L.tof[k] = St.temp_of[sy.walker0 + k];
   }
   for (int k = tid; k < 256; k += nthr) L.nacc[k] = 0u;
-  if (tid == 0) L.misc[0] = L.misc[1] = 0;
+  if (tid == 0) L.misc[0] = 0;
 }
 
 // Write the swap state back after n_rounds rounds numbered from rounds0: the
 // stream window (oldest word first), labels, per-slot attempts (slot k takes
-// part in the rounds whose parity is k mod 2) and acceptances, and the
-// near-threshold count.
+// part in the rounds whose parity is k mod 2) and acceptances.
 static __device__ void ladder_store(const DevState &St, const SysInfo &sy, int sys, int tid, int nthr,
                                     const LadderLds &L, int64_t rounds0, int64_t n_rounds) {
   const int h = L.misc[0];
@@ -127,7 +129,6 @@ static __device__ void ladder_store(const DevState &St, const SysInfo &sy, int s
       if (L.nacc[k]) St.swap_acc[sy.slot0 + k] += (unsigned long long)L.nacc[k];
     }
   }
-  if (tid == 0 && L.misc[1]) atomicAdd((unsigned long long *)&St.stats[0], (unsigned long long)L.misc[1]);
 }
 
 }  // namespace ising

@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
         __syncthreads();
         const int parity = (int)((la.rounds0 + n_rounds) & 1);
         const int np = ladder_swap_round(sy, parity, tid, L, pb.lo(parity), pb.hi(parity), lds, PW,
-                                         ZP + FW + SWW + TRW);
+                                         ZP + FW + SWW + TRW, (unsigned long long *)St.swap_near + sy.slot0);
         ++n_rounds;
         for (int i = tid; i < np * TRW; i += nthr) {
           const int j = i / TRW, wd = i - j * TRW;
@@ -460,14 +460,11 @@ template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>
 static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bucket &b,
                                  int32_t n_sweeps, int32_t init_mode, hipStream_t st, LadderArgs la) {
   auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER, TF>;
-  // Allow the whole LDS once per instantiation (outside any stream capture
-  // after the first launch of a variant).
-  static bool lds_limit_set = false;
-  if (!lds_limit_set && b.lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+  // Allow the whole LDS once per instantiation and device.
+  static std::atomic<uint64_t> lds_limit_set{0};
+  if (b.lds > 64 * 1024) {
+    hipError_t e = allow_lds(kern, 160 * 1024, lds_limit_set);
     if (e != hipSuccess) return e;
-    lds_limit_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(b.ntiles), dim3(b.threads), b.lds, st, t, s, b.tile0, b.G, b.tpw,
                      b.walker_words, n_sweeps, init_mode, la);

@@ -52,6 +52,11 @@ def compare_system(st, s, ch, what=""):
     assert np.array_equal(st.host("flips")[w0:w1].astype(np.uint64), c["flips"]), f"{what} flips"
     assert np.array_equal(st.host("swap_att")[slot0:slot0 + (w1 - w0)].astype(np.uint64), c["swap_att"])
     assert np.array_equal(st.host("swap_acc")[slot0:slot0 + (w1 - w0)].astype(np.uint64), c["swap_acc"])
+    gnear = st.host("swap_near")[slot0:slot0 + (w1 - w0)].astype(np.uint64)
+    assert np.array_equal(gnear, c["swap_near"]), \
+        f"{what} system {s}: near-threshold swap counts differ: gpu {gnear.tolist()} oracle {c['swap_near'].tolist()}"
+    if c["near"]:
+        say(f"{what} system {s}: near-threshold swap decisions at pairs", np.nonzero(c["swap_near"])[0].tolist())
     return c["near"]
 
 

@@ -120,6 +120,28 @@ def test_validation_error_codes(kw, code):
     assert e.value.code == code
 
 
+def test_cold_ladder_range():
+    """A flip probability exp(-2 beta d) that would underflow to 0 in double has no
+    uint32 threshold (u <= thr cannot say "never"; a wrapped ceil - 1 would say
+    "always").  Rows stay exact up to 2 beta d_max = 700 and are rejected beyond, and
+    a system is checked with its own d_max, not the table's 63."""
+    for beta, dmax in ((12.0, 27), (5.5, 63), (350.0, 1), (20.0, 17)):
+        row = pa.threshold_row(beta, dmax)
+        assert row[0] == 0xFFFFFFFF
+        assert all(0 <= int(row[d]) < 0xFFFFFFFF for d in range(1, dmax + 1))
+        assert all(row[d] >= row[d + 1] for d in range(1, dmax))
+        assert int(row[dmax]) == _exact_threshold(beta, dmax) - 1 or int(row[dmax]) == 0
+    for beta, dmax in ((20.0, 27), (5.6, 63), (350.1, 1)):
+        with pytest.raises(pa.IsingError) as e:
+            pa.threshold_row(beta, dmax)
+        assert e.value.code == -2
+    # the system of _bad() has d_max = max over spins of |h| + sum|J| + 2 |J_tau| <= 21
+    pa.level_offsets(_bad(beta=np.array([0.5, 6.0])))  # 2 * 6 * 21 <= 700
+    with pytest.raises(pa.IsingError) as e:
+        pa.level_offsets(_bad(beta=np.array([0.5, 60.0])))
+    assert e.value.code == -2
+
+
 def test_validation_degree():
     S = 12
     eu = np.array([0] * 9, np.int32)

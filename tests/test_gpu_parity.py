@@ -25,6 +25,7 @@ def _run_compare(wl, idx, steps, swap_every, record=False):
     near = 0
     for n in steps:
         e = st.sweep(n, swap_every, record=record)
+        near = 0  # the counts are cumulative: keep the last comparison's total
         for s, ch in zip(idx, chains):
             rec = ch.sweeps(n, swap_every, record_energy=record)
             near += compare_system(st, s, ch, f"after {st.sweeps} sweeps")
@@ -39,7 +40,8 @@ def test_parity_config_A_every_sweep():
     first 40 sweeps, then after the remaining 960 (1000 in all)."""
     wl = make_workload("A")
     g, st, near = _run_compare(wl, [0], [1] * 40 + [960], 1)
-    say("near-threshold swap decisions", near, "gpu", int(st.host("stats")[0]))
+    say("near-threshold swap decisions, oracle", near, "gpu", st.stats()["near"])
+    assert st.stats()["near"] == near
     assert st.sweeps == 1000 and st.rounds == 1000
 
 

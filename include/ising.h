@@ -344,6 +344,16 @@ int32_t ising_mlp_forward(const ising_mlp *net, const float *x, int32_t n, float
  * result depends only on the batch (bitwise reproducible). */
 int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n, float *loss,
                        void *stream);
+/* The same gradient step for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): net->part is not used (it may be NULL);
+ * the partial gradients go to a fixed array of the library, ISING_MLP_PARTS x
+ * (ISING_MLP_PARAMS + 1) floats (10,162,688 bytes) per GPU, held until the
+ * process ends.  Every batch size needs at most those rows (ISING_E_SIZE
+ * otherwise).  The result equals ising_mlp_grad's bit for bit.  Nothing is
+ * allocated; calls that overlap on one GPU share the array and race. */
+int32_t ising_mlp_grad_noalloc(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n, float *loss,
+                               void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with net->grad, then repack. */
 int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream);
 

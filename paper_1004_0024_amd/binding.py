@@ -79,6 +79,7 @@ def lib():
             "ising_mlp_pack": ([P, P], i32),
             "ising_mlp_forward": ([P, P, i32, P, P], i32),
             "ising_mlp_grad": ([P, P, P, i32, P, P], i32),
+            "ising_mlp_grad_noalloc": ([P, P, P, i32, P, P], i32),
             "ising_mlp_adam": ([P, C.c_float, P], i32),
             "ising_collect_cells": ([P, P, i64, i64, i32, P, P, P], i32),
             "ising_propose_cells": ([P, P, P, C.c_uint64, i64, P, P], i32),
@@ -478,6 +479,12 @@ class Mlp:
         _check(lib().ising_mlp_grad(C.byref(self._s), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                     int(x.shape[0]), C.c_void_p(loss.data_ptr()), _stream()))
         return loss
+
+    def grad_step_noalloc(self, x, y, loss):
+        """The same step with the library's own partial-gradient rows (nothing allocated by
+        the library; x, y and the device scalar `loss` are the caller's)."""
+        _check(lib().ising_mlp_grad_noalloc(C.byref(self._s), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                            int(x.shape[0]), C.c_void_p(loss.data_ptr()), _stream()))
 
     def adam(self, lr):
         _check(lib().ising_mlp_adam(C.byref(self._s), C.c_float(lr), _stream()))

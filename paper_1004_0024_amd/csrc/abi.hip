@@ -758,6 +758,19 @@ extern "C" int32_t ising_mlp_grad(const ising_mlp *net, const float *x, const ui
   return ISING_OK;
 }
 
+extern "C" int32_t ising_mlp_grad_noalloc(const ising_mlp *net, const float *x, const uint8_t *y, int32_t n,
+                                          float *loss, void *stream) {
+  if (!net || !net->w || !net->grad || !net->wb) return fail(ISING_E_INVAL, "mlp_grad_noalloc: NULL buffer");
+  if (n < 1 || !x || !y) return fail(ISING_E_INVAL, "mlp_grad_noalloc: bad arguments");
+  if (mlp_grad_parts(n) > ISING_MLP_PARTS)
+    return fail(ISING_E_SIZE, "mlp_grad_noalloc: %d partial gradients exceed the %d rows of the library's scratch",
+                mlp_grad_parts(n), ISING_MLP_PARTS);
+  float *rows = nullptr;
+  HIP_TRY(mlp_scratch_rows(&rows), "mlp_grad_noalloc: scratch address");
+  HIP_TRY(launch_mlp_grad(net->w, net->wb, x, y, n, rows, net->grad, loss, (hipStream_t)stream), "mlp grad");
+  return ISING_OK;
+}
+
 extern "C" int32_t ising_mlp_adam(ising_mlp *net, float lr, void *stream) {
   int32_t rc = check_mlp(net);
   if (rc) return rc;

@@ -45,6 +45,9 @@ hipError_t launch_mlp_forward(const float *w, const uint16_t *wb, const float *x
 int mlp_grad_parts(int32_t n);
 hipError_t launch_mlp_grad(const float *w, const uint16_t *wb, const float *x, const uint8_t *y, int32_t n,
                            float *part, float *grad, float *loss, hipStream_t st);
+// Device address of the library's own partial-gradient rows (kMlpParts x
+// (kNParams + 1) floats) on the current device.
+hipError_t mlp_scratch_rows(float **rows);
 hipError_t launch_adam(float *w, float *m, float *v, const float *g, int32_t n, float lr, float b1, float b2,
                        float eps, int64_t t, hipStream_t st);
 

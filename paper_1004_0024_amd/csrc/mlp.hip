@@ -413,4 +413,34 @@ hipError_t launch_adam(float *w, float *m, float *v, const float *g, int32_t n, 
   return hipGetLastError();
 }
 
+// ---- gradient step without caller scratch ------------------------------------
+// The partial gradients of mlp_grad_kernel in a fixed device array, for callers
+// that cannot allocate (graph capture, serving loops): kMlpParts rows of
+// kNParams + 1 floats, 10,162,688 bytes per GPU, held until the process ends.
+// Every launch writes each entry of the rows it uses (its kNParams + 1 floats)
+// and the reduction reads only those rows, so nothing needs clearing between
+// calls; two calls that overlap on one GPU share the rows and race.
+static __device__ __align__(256) float scratch[kMlpParts * (kNParams + 1)];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (the array's host-side name is not a device address).
+static std::atomic<float *> scratch_ptr[64];
+
+hipError_t mlp_scratch_rows(float **rows) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  float *p = scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    void *q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    p = (float *)q;
+    scratch_ptr[dev].store(p, std::memory_order_release);
+  }
+  *rows = p;
+  return hipSuccess;
+}
+
 }  // namespace ising

@@ -269,24 +269,27 @@ def pairs_leg(name, n_sweeps, reps):
             "flip_rate": stats["flips"] / max(1, g.attempts_per_sweep * st.sweeps)}
 
 
-def learned_leg(ess_steps, train_rows=1 << 20):
+def learned_leg(ess_steps, train_rows=1 << 20, burn_in=20000):
     """Learned cell proposal on the 256 x 32-walker, 4,096-spin workload: train the
     network on the GPU from plain-chain samples, then effective samples per second of
     the plain chain (sweep + swap round per step) against the learned chain (sweep +
     swap round + one pass of learned cell moves per step) and the heat-bath chain (the
-    same with exact heat-bath cell moves), all from the same state."""
+    same with exact heat-bath cell moves), all from the same state after `burn_in`
+    plain sweeps.  The ratios are taken at matched observable accuracy: at the ladder
+    positions where both cell-move chains' slot mean energies agree with the plain
+    chain's within 4 combined standard errors for at least 99% of the systems."""
     import numpy as np
     import torch
 
     import paper_1004_0024_amd as pa
-    from paper_1004_0024_amd import learn
+    from paper_1004_0024_amd import learn, tune
     from gen import make_workload
     from gen.mlp import initial_params
 
     wl = make_workload("E")
     g = pa.Graph(wl.systems)
     st = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
-    st.sweep(3000, 1)  # burn-in
+    st.sweep(burn_in, 1)
     t0 = time.perf_counter()
     x, y = learn.collect(st, train_rows, snapshots=8, sweeps_between=5)
     net = pa.Mlp(initial_params(11))
@@ -353,20 +356,37 @@ def learned_leg(ess_steps, train_rows=1 << 20):
             row[name] = {"ms_per_step": r["ms"] / (ess_steps // 2), "ess_coldest": e["coldest_total"],
                          "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3)}
         cell_cadence.append(row)
-    # swap cadence (it changes the chain; the objective is effective samples per second)
-    cadence = []
-    for every in (1, 2, 4, 8):
-        s2 = pa.State(g).copy_from(base)
-        r = learn.run(s2, ess_steps // 2, None, swap_every=every)
-        e = learn.ess_summary(g, r["e"])
-        cadence.append({"swap_every": every, "ms_per_step": r["ms"] / (ess_steps // 2),
-                        "ess_coldest": e["coldest_total"], "ess_median_slot": e["median_slot"],
-                        "ess_per_s": e["coldest_total"] / (r["ms"] / 1e3)})
+    # swap cadence, tuned by effective samples per second (it changes the chain)
+    cadence = tune.swap_cadence(base, (1, 2, 4, 8), ess_steps // 2)
+    # matched observable accuracy: the ladder positions where both cell-move chains agree
+    # with the plain chain; ESS per second there
+    ms_total = {name: chains[name]["ms_per_step"] * ess_steps for name in chains}
+    slots, comp = learn.matched_slots(g, series)
+    matched = {"criterion": "ladder positions where the learned and the heat-bath chain's slot mean "
+                            "energies agree with the plain chain's, |z| < 4 (combined standard error from "
+                            "variance / ESS), for at least 99% of the 256 systems",
+               "slots": slots,
+               "frac_below_4_by_slot": {k: v["frac_below_4_by_slot"] for k, v in comp.items()}}
+    if slots:
+        kc = max(slots)  # the coldest matched position (beta ascends along the ladder)
+        per_s = {name: learn.slot_ess_totals(g, series[name], [kc])[kc] / (ms_total[name] / 1e3)
+                 for name in chains}
+        tot = {name: sum(learn.slot_ess_totals(g, series[name], slots).values()) / (ms_total[name] / 1e3)
+               for name in chains}
+        matched.update({
+            "coldest_matched_slot": kc, "beta": float(wl.systems[0].beta[kc]),
+            "ess_per_s_at_slot": per_s,
+            "learned_over_plain": per_s["learned"] / per_s["plain"],
+            "heatbath_over_plain": per_s["heatbath"] / per_s["plain"],
+            "summed_over_matched_slots": {"learned_over_plain": tot["learned"] / tot["plain"],
+                                          "heatbath_over_plain": tot["heatbath"] / tot["plain"]}})
     return {
-        "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": 3000,
+        "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": burn_in,
+        "matched_accuracy": matched,
         "swap_cadence": cadence,
         "cell_cadence": cell_cadence,
-        "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems",
+        "ess": "energy at the coldest slot (beta 3.0), Sokal window c=5, first 20% dropped, summed over systems; "
+               "the coldest slot is not matched (see matched_accuracy)",
         "train": {"rows": int(x.shape[0]), "batch": 4096, "adam_steps": int(len(losses)),
                   "loss_untrained": loss0, "loss_last": float(losses[-1]), "seconds": train_s},
         "acceptance_one_pass": acc,
@@ -376,8 +396,7 @@ def learned_leg(ess_steps, train_rows=1 << 20):
         "heatbath_kernel_ms": hb_ms,
         # slot mean energies of the cell-move chains against the plain chain, in combined
         # standard errors (per system and slot)
-        "means_vs_plain": {"learned": learn.compare_means(g, series["learned"], series["plain"]),
-                           "heatbath": learn.compare_means(g, series["heatbath"], series["plain"])},
+        "means_vs_plain": comp,
         "roofline": {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
                      "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,
@@ -401,6 +420,8 @@ def main():
     ap.add_argument("--no-pairs", action="store_true", help="skip the layer-pair order leg")
     ap.add_argument("--ess-steps", type=int, default=10000,
                     help="chain steps per ESS estimate in the learned-proposal leg")
+    ap.add_argument("--burn-in", type=int, default=20000,
+                    help="plain sweeps before the learned-proposal leg collects and compares")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole path runs on a single MI355X "
@@ -529,7 +550,7 @@ def main():
         out["layer_pairs"] = [pairs_leg("B", 100, max(2, args.steps // 2)), pairs_leg("A", 1000, 3)]
         progress("layer-pair order done")
     if not args.no_learned:
-        out["effective_samples"] = learned_leg(args.ess_steps)
+        out["effective_samples"] = learned_leg(args.ess_steps, burn_in=args.burn_in)
         progress("learned proposal done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

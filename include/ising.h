@@ -128,7 +128,14 @@ int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row
  *   ising_sweep runs the swap rounds inside the sweep kernel, one launch per
  *   call; the chain is the same).
  * set_launch returns ISING_E_RANGE for a shape that does not fit (threads,
- * LDS, columns per thread) and leaves the bucket unchanged.                  */
+ * LDS, columns per thread) and leaves the bucket unchanged.
+ * With several buckets a sweep forks side streams (default priority) from the
+ * caller's stream and joins them before it returns: at most as many streams
+ * as the process has hardware queues (GPU_MAX_HW_QUEUES, HIP's default 4),
+ * since kernels that share a queue run one after another.  The buckets are
+ * enqueued largest first, each onto the stream with the least work so far;
+ * the work of a bucket is its attempts per sweep, or its time per sweep once
+ * ising_autotune has measured it.                                            */
 int32_t ising_n_buckets(const ising_graph *g);
 int32_t ising_bucket_info(const ising_graph *g, int32_t bucket, int64_t *out, int32_t n);
 int32_t ising_set_launch(ising_graph *g, int32_t bucket, int32_t tpw, int32_t walkers_per_group,
@@ -209,8 +216,9 @@ void ising_replay_free(ising_replay *r);
  * report[report_rows][4].  A ladder bucket only tries ladder shapes (its
  * swap rounds stay inside the kernel); when every bucket is one, each timed
  * launch runs 16 sweeps with a swap round after each, as ising_sweep runs
- * them, and the report gives the time per sweep.  Returns the number of rows
- * written (>= 0) or an error code.  Synchronous.                             */
+ * them, and the report gives the time per sweep.  The kept shapes' times per
+ * sweep then spread the buckets over the sweep's streams.  Returns the number
+ * of rows written (>= 0) or an error code.  Synchronous.                     */
 int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream, int64_t *report,
                        int32_t report_rows);
 

@@ -27,3 +27,4 @@ from .binding import (  # noqa: F401
     trotter_weights,
     two_field_row,
 )
+from . import tune  # noqa: F401,E402  (swap cadence by effective samples per second)

@@ -32,11 +32,11 @@ static int32_t hip_fail(hipError_t e, const char *where) {
 struct ising_graph : GraphPlan {
   DevTables dev{};
   size_t bytes = 0;
-  // With several buckets, bucket b > 0 is launched on side[b - 1] (forked from
-  // and joined back to the caller's stream), so the buckets of one sweep run
-  // side by side and each one's tail overlaps the others.
+  // With several buckets, stream q > 0 of the plan (stream_of) is side[q - 1],
+  // forked from and joined back to the caller's stream, so the buckets of one
+  // sweep run side by side and each one's tail overlaps the others.
   std::vector<hipStream_t> side;
-  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[b]: bucket b done
+  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[q]: stream q done
   ~ising_graph() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (hipStream_t q : side) (void)hipStreamDestroy(q);
@@ -155,8 +155,8 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.qwt = 2 * g->qdt + 1;
   g->dev.qoff = g->qds * (2 * g->qdt + 1) + g->qdt;
   g->bytes = L.total;
-  if (g->buckets.size() > 1) {
-    for (size_t b = 0; b < g->buckets.size(); ++b) {
+  if (g->n_streams > 1) {
+    for (int32_t b = 0; b < g->n_streams; ++b) {
       hipEvent_t ev;
       e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
       if (e != hipSuccess) break;
@@ -385,21 +385,24 @@ extern "C" int32_t ising_init_state(const ising_graph *g, ising_state *st, const
 
 // Enqueue n_sweeps sweeps (and the swap rounds due) starting from the
 // counters *sweeps / *rounds, advancing them.
-// Launch every bucket (bucket b > 0 on side stream b - 1 when there are several,
+// Launch every bucket, largest first: on the caller's stream s, or with several
+// streams each bucket on its stream of the plan (side streams forked from and
 // joined back to s).
 static int32_t launch_buckets(const ising_graph *g, const DevState &d, int32_t n, LadderArgs la, hipStream_t s) {
   if (g->side.empty()) {
-    for (const Bucket &b : g->buckets) HIP_TRY(launch_sweep(g->dev, d, b, n, 0, s, la), "sweep kernel");
+    for (int32_t b : g->launch_order) HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], n, 0, s, la), "sweep kernel");
     return ISING_OK;
   }
   HIP_TRY(hipEventRecord(g->ev[0], s), "fork");
-  for (size_t b = 1; b < g->buckets.size(); ++b) {
-    HIP_TRY(hipStreamWaitEvent(g->side[b - 1], g->ev[0], 0), "fork wait");
-    HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], n, 0, g->side[b - 1], la), "sweep kernel");
-    HIP_TRY(hipEventRecord(g->ev[b], g->side[b - 1]), "join record");
+  for (size_t q = 0; q < g->side.size(); ++q) HIP_TRY(hipStreamWaitEvent(g->side[q], g->ev[0], 0), "fork wait");
+  for (int32_t b : g->launch_order) {
+    const int32_t q = g->stream_of[b];
+    HIP_TRY(launch_sweep(g->dev, d, g->buckets[b], n, 0, q == 0 ? s : g->side[q - 1], la), "sweep kernel");
   }
-  HIP_TRY(launch_sweep(g->dev, d, g->buckets[0], n, 0, s, la), "sweep kernel");
-  for (size_t b = 1; b < g->buckets.size(); ++b) HIP_TRY(hipStreamWaitEvent(s, g->ev[b], 0), "join");
+  for (size_t q = 0; q < g->side.size(); ++q) {
+    HIP_TRY(hipEventRecord(g->ev[q + 1], g->side[q]), "join record");
+    HIP_TRY(hipStreamWaitEvent(s, g->ev[q + 1], 0), "join");
+  }
   return ISING_OK;
 }
 
@@ -529,7 +532,8 @@ extern "C" void ising_replay_free(ising_replay *r) {
 // ---------------------------------------------------------------------------
 // Autotuner: time every admissible launch shape of every bucket on a scratch
 // state (single-sweep launches, as in a swap-every-sweep loop) and keep the
-// fastest.  The chain does not depend on the shape.
+// fastest; the kept shapes' times then spread the buckets over the streams.
+// The chain does not depend on the shape.
 // ---------------------------------------------------------------------------
 extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void *stream,
                                   int64_t *report, int32_t report_rows) {
@@ -589,7 +593,10 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
       }
     }
     g->buckets[bi] = best;
+    if (best_ns > 0) g->bucket_cost[bi] = best_ns;  // the bucket's own time per sweep
   }
+  // spread the buckets over the streams by their measured times
+  assign_streams(*g, (int32_t)g->side.size() + 1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   retile(*g);

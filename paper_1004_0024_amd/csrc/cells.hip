@@ -113,10 +113,31 @@ __device__ __forceinline__ int cell_energy(uint32_t byte, const int b[8], const 
   return e;
 }
 
+// E_c(s') - E_c(s) with packed byte products: for a cell byte s (bit k = spin k
+// is +1), sum_k b_k s_k = 2 sum_k b_k bit_k - sum_k b_k, and for a left spin k,
+// 2 sum_r J_kr s_r = 2 sum_r 2J_kr bit_r - sum_r 2J_kr, each sum one 4-way byte
+// dot product.  blo / bhi hold b_0..b_3 / b_4..b_7 as signed bytes (|b| <= 63),
+// jpack[k] the 2J of left spin k to right spins 0..3, jsum2[k] their sum.
+__device__ __forceinline__ uint32_t spread4(uint32_t nib) { return __umul24(nib, 0x00204081u) & 0x01010101u; }
+
+__device__ __forceinline__ int cell_energy_packed(uint32_t byte, uint32_t blo, uint32_t bhi, int bsum,
+                                                  const int32_t jpack[4], const int jsum2[4]) {
+  const uint32_t sl = spread4(byte & 15u), sr = spread4(byte >> 4);
+  const int bs = 2 * (__builtin_amdgcn_sdot4((int)sl, (int)blo, 0, false) +
+                      __builtin_amdgcn_sdot4((int)sr, (int)bhi, 0, false)) - bsum;  // sum_k b_k s_k
+  int js2 = 0;  // 2 sum_{k, r} J_kr s_k s_r
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int t = 2 * __builtin_amdgcn_sdot4((int)sr, jpack[k], 0, false) - jsum2[k];
+    js2 += ((byte >> k) & 1u) ? t : -t;
+  }
+  return -bs - js2 / 2;
+}
+
 // ---- rows of a colour class ---------------------------------------------------
 // Row = (walker, cell of the class).  A 64-row tile lies in one system (rows
-// of a system start at a multiple of 64), so its record is read once for the
-// wavefront.
+// of a system start at a multiple of 64); the fields of that system are read
+// once per tile into wavefront-uniform registers.
 struct CellRow {
   bool valid;
   int r, ci;           // global walker, cell index (m*L + y)*L + x
@@ -127,35 +148,133 @@ struct CellRow {
   uint32_t cur;        // its current value (bit k = spin k is +1)
 };
 
-__device__ __forceinline__ void load_cell_row(const DevTables &T, const DevState &St, int64_t tile, int lane,
-                                              int32_t phase, CellRow &c) {
+struct TileSys {
+  int M, L, LL, RS, WW, ring, K, walker0, slot0, cb0, rows, cl0, p0, count, fast;
+  long long spin_word0, row0;
+};
+
+__device__ __forceinline__ long long uniform64(long long v) {
+  return ((long long)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+         (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ TileSys tile_system(const DevTables &T, int64_t tile, int phase) {
   const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
-  const SysInfo &sy = T.sys[sidx];
-  const int64_t row = tile * 64 + lane;
-  // rows of one system: K x rows < 2^31 (a walker's spins fit in LDS)
-  const uint32_t local = (uint32_t)(row - sy.row0);
-  const uint32_t rows = (uint32_t)sy.rows;
-  const int wk = (int)(local / rows), j = (int)(local - (uint32_t)wk * rows);
-  const int count = phase < sy.n_phases ? sy.pc[phase + 1] - sy.pc[phase] : 0;
-  c.valid = wk < sy.K && j < count;
-  c.r = -1;
-  c.ci = 0;
-  for (int k = 0; k < 8; ++k) c.b[k] = 0;
-  for (int k = 0; k < 4; ++k) c.jpack[k] = 0;
-  c.beta = 0.f;
-  c.bytep = nullptr;
-  c.cur = 0;
-  if (c.valid) {
-    c.r = sy.walker0 + wk;
-    c.ci = T.cells[sy.cl0 + sy.pc[phase] + j];
-    const int LL = sy.grid_L * sy.grid_L;
-    const int m = c.ci / LL, cc = c.ci - m * LL;
-    const uint32_t *sp = St.spins + sy.spin_word0 + (size_t)wk * sy.WW;
-    boundary_fields(T, sy, sp, m, cc, c.b, c.jpack);
-    c.bytep = (uint8_t *)(St.spins + sy.spin_word0 + (size_t)wk * sy.WW + m * sy.RS + ((cc * 8) >> 5)) + (cc & 3);
-    c.cur = *c.bytep;
-    c.beta = (float)T.beta[sy.slot0 + St.temp_of[c.r]];
+  const SysInfo *sy = T.sys + sidx;
+  TileSys u;
+  u.M = __builtin_amdgcn_readfirstlane(sy->M);
+  u.L = __builtin_amdgcn_readfirstlane(sy->grid_L);
+  u.LL = u.L * u.L;
+  u.RS = __builtin_amdgcn_readfirstlane(sy->RS);
+  u.WW = __builtin_amdgcn_readfirstlane(sy->WW);
+  u.ring = __builtin_amdgcn_readfirstlane(sy->ring);
+  u.K = __builtin_amdgcn_readfirstlane(sy->K);
+  u.walker0 = __builtin_amdgcn_readfirstlane(sy->walker0);
+  u.slot0 = __builtin_amdgcn_readfirstlane(sy->slot0);
+  u.cb0 = __builtin_amdgcn_readfirstlane(sy->cb0);
+  u.rows = __builtin_amdgcn_readfirstlane(sy->rows);
+  u.cl0 = __builtin_amdgcn_readfirstlane(sy->cl0);
+  u.fast = __builtin_amdgcn_readfirstlane(sy->cell_fast);
+  const int np = __builtin_amdgcn_readfirstlane(sy->n_phases);
+  u.p0 = phase < np ? __builtin_amdgcn_readfirstlane(sy->pc[phase]) : 0;
+  u.count = phase < np ? __builtin_amdgcn_readfirstlane(sy->pc[phase + 1]) - u.p0 : 0;
+  u.spin_word0 = uniform64(sy->spin_word0);
+  u.row0 = uniform64(sy->row0);
+  return u;
+}
+
+// The lane's row: its walker and cell, the cell's boundary fields b_k = h_k +
+// sum_{j outside the cell} J_kj s_j, in-cell couplings, byte and beta.  Every
+// load is issued before any is used: the cell list entry and the walker's
+// slot, then the seven spin words around the cell (the cells above, below,
+// left and right in its slice, the cell itself, and the cell in the slices
+// before and after), its record and beta.  In-slice edges between cells join
+// grid neighbours only (checked when the graph is loaded), so a neighbour's
+// bit lies in one word that packs the four neighbour cells' bytes.  With
+// cell_fast the neighbours of spin k are spin k of each neighbour cell: the
+// four bits are (word >> k) & 0x01010101 and one byte dot product with the
+// couplings by direction sums them; otherwise each of the record's entries
+// names the neighbour's bit.
+__device__ __forceinline__ void load_row(const DevTables &T, const DevState &St, const TileSys &u, int64_t tile,
+                                         int lane, CellRow &c) {
+  const uint32_t local = (uint32_t)(tile * 64 + lane - u.row0);
+  const int wk = (int)(local / (uint32_t)u.rows), j = (int)(local - (uint32_t)wk * (uint32_t)u.rows);
+  c.valid = wk < u.K && j < u.count;
+  const int wkc = c.valid ? wk : 0, jc = c.valid ? j : 0;
+  c.r = c.valid ? u.walker0 + wk : -1;
+  const int ci = (int)T.cells[u.cl0 + u.p0 + jc];
+  const int tof = St.temp_of[u.walker0 + wkc];
+  c.ci = ci;
+  const int m = ci / u.LL, cc = ci - m * u.LL;
+  const int y = cc / u.L, x = cc - y * u.L;
+  const uint32_t *sp = St.spins + u.spin_word0 + (size_t)wkc * u.WW;
+  const uint32_t *row = sp + m * u.RS;
+  const int mp = m == 0 ? u.M - 1 : m - 1, mn = m == u.M - 1 ? 0 : m + 1;
+  const bool has_p = u.M > 1 && (m > 0 || u.ring), has_n = u.M > 1 && (m < u.M - 1 || u.ring);
+  const int cu = y > 0 ? cc - u.L : cc, cd = y < u.L - 1 ? cc + u.L : cc;
+  const int cl = x > 0 ? cc - 1 : cc, cr = x < u.L - 1 ? cc + 1 : cc;
+  const uint32_t wu = row[cu >> 2], wdn = row[cd >> 2], wl = row[cl >> 2], wr = row[cr >> 2], wo = row[cc >> 2];
+  const uint32_t wp = sp[mp * u.RS + (cc >> 2)], wn = sp[mn * u.RS + (cc >> 2)];
+  const uint4 *rec = (const uint4 *)(T.cellrec + (size_t)(u.cb0 + cc) * kCellRecWords);
+  const uint4 hq = rec[4], jq = rec[5];
+  auto cell_byte = [](uint32_t w, int q) { return (w >> ((q & 3) * 8)) & 0xffu; };
+  const uint32_t nbytes = cell_byte(wu, cu) | (cell_byte(wdn, cd) << 8) | (cell_byte(wl, cl) << 16) |
+                          (cell_byte(wr, cr) << 24);
+  const uint32_t bp = has_p ? cell_byte(wp, cc) : 0u, bn = has_n ? cell_byte(wn, cc) : 0u;
+  if (u.fast) {
+    const uint4 d0 = rec[6], d1 = rec[7];
+    const uint32_t dir[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int h = (int)(int8_t)((((k < 4) ? hq.x : hq.y) >> (8 * (k & 3))) & 0xffu);
+      const int jtau = (int)(int8_t)((((k < 4) ? hq.z : hq.w) >> (8 * (k & 3))) & 0xffu);
+      // h + sum_dir J (2 bit - 1) = h + sum 2J bit - sum 2J / 2
+      int f = h + __builtin_amdgcn_sdot4((int)((nbytes >> k) & 0x01010101u), (int)dir[k], 0, false) -
+              (__builtin_amdgcn_sdot4(0x01010101, (int)dir[k], 0, false) >> 1);
+      if (has_p) f += jtau * (2 * (int)((bp >> k) & 1u) - 1);
+      if (has_n) f += jtau * (2 * (int)((bn >> k) & 1u) - 1);
+      c.b[k] = c.valid ? f : 0;
+    }
+  } else {
+    const uint4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+    const uint32_t ent[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                              r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int f = (int)(int8_t)((((k < 4) ? hq.x : hq.y) >> (8 * (k & 3))) & 0xffu);
+      const int jtau = (int)(int8_t)((((k < 4) ? hq.z : hq.w) >> (8 * (k & 3))) & 0xffu);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {  // an unused entry has J = 0
+        const uint32_t v = ent[2 * k + (e >> 1)] >> (16 * (e & 1));
+        const int J = (int)(int8_t)(v & 0xffu);
+        const int bit = (int)((nbytes >> ((v >> 8) & 31u)) & 1u);
+        f += J * (2 * bit - 1);
+      }
+      if (has_p) f += jtau * (2 * (int)((bp >> k) & 1u) - 1);
+      if (has_n) f += jtau * (2 * (int)((bn >> k) & 1u) - 1);
+      c.b[k] = c.valid ? f : 0;
+    }
   }
+  c.jpack[0] = (int32_t)jq.x;
+  c.jpack[1] = (int32_t)jq.y;
+  c.jpack[2] = (int32_t)jq.z;
+  c.jpack[3] = (int32_t)jq.w;
+  c.bytep = (uint8_t *)(St.spins + u.spin_word0 + (size_t)wkc * u.WW + m * u.RS + (cc >> 2)) + (cc & 3);
+  c.cur = cell_byte(wo, cc);
+  c.beta = c.valid ? (float)T.beta[u.slot0 + tof] : 0.f;
+}
+
+// This wavefront's tiles: a contiguous run (the rows of one walker, then the
+// next), so a walker's spin words and its system's records stay in cache.
+struct TileRange {
+  int64_t begin, end;
+};
+__device__ __forceinline__ TileRange wave_tiles(int64_t tiles, int waves_per_group) {
+  const int64_t nwaves = (int64_t)gridDim.x * waves_per_group;
+  const int64_t per = (tiles + nwaves - 1) / nwaves;
+  const int64_t w = (int64_t)blockIdx.x * waves_per_group + (threadIdx.x >> 6);
+  const int64_t b = w * per;
+  return TileRange{b < tiles ? b : tiles, b + per < tiles ? b + per : tiles};
 }
 
 // Per-walker sums of a wavefront's rows: energy change, rows, rows counted in
@@ -271,12 +390,11 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
 
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, n16 = l & 15, g = l >> 4;
   uint16_t *X = s.X[wv];
-  const int64_t tiles = rows_total / 64;  // rows_total is a multiple of 64
-  for (int64_t tile = (int64_t)blockIdx.x * kProposeWaves + wv; tile < tiles;
-       tile += (int64_t)gridDim.x * kProposeWaves) {
+  const TileRange tr = wave_tiles(rows_total / 64, kProposeWaves);  // rows_total is a multiple of 64
+  for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     // ---- this lane's row: locate the cell, boundary fields, input ----
     CellRow cr;
-    load_cell_row(T, St, tile, l, phase, cr);
+    load_row(T, St, tile_system(T, tile, phase), tile, l, cr);
     const bool valid = cr.valid;
     const int *b = cr.b;
     const float beta = cr.beta;
@@ -360,11 +478,6 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       float lg[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) lg[k] = Lg[l * 8 + k];
-      int jin[16];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) jin[k * 4 + i] = ((int32_t)(int8_t)((cr.jpack[k] >> (8 * i)) & 0xff)) / 2;
       const uint32_t cur = cr.cur;
       const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
       uint32_t wd[12];
@@ -379,17 +492,30 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       float lratio = 0.f;  // log q(current) - log q(proposed)
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
+        // u < sigmoid(l)  <=>  u (1 + e^-l) < 1 (hardware exponential, FP32)
         const float u = (float)wd[k] * 0x1p-32f;
-        const bool up = u < 1.f / (1.f + expf(-lg[k]));
+        const bool up = u * (1.f + __expf(-lg[k])) < 1.f;
         nb |= (up ? 1u : 0u) << k;
         // log s(x) - log s(-x) = x: only the spins that change contribute
         const bool was_up = (cur >> k) & 1u;
         if (up != was_up) lratio += was_up ? lg[k] : -lg[k];
       }
-      dE = cell_energy(nb, b, jin) - cell_energy(cur, b, jin);
+      {
+        uint32_t blo = 0, bhi = 0;
+        int bsum = 0, jsum2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          blo |= (uint32_t)(b[k] & 0xff) << (8 * k);
+          bhi |= (uint32_t)(b[4 + k] & 0xff) << (8 * k);
+          bsum += b[k] + b[4 + k];
+          jsum2[k] = __builtin_amdgcn_sdot4(0x01010101, cr.jpack[k], 0, false);
+        }
+        dE = cell_energy_packed(nb, blo, bhi, bsum, cr.jpack, jsum2) -
+             cell_energy_packed(cur, blo, bhi, bsum, cr.jpack, jsum2);
+      }
       const float la = -beta * (float)dE + lratio;
       const float ua = (float)wd[8] * 0x1p-32f;
-      accept = la >= 0.f || ua < expf(la);
+      accept = la >= 0.f || ua < __expf(la);
       if (accept && nb != cur) *cr.bytep = (uint8_t)nb;
       if (!accept) dE = 0;
     }
@@ -420,11 +546,11 @@ hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_
 __global__ void __launch_bounds__(256) cell_heatbath_kernel(DevTables T, DevState St, int64_t rows_total,
                                                             int32_t phase, uint64_t key, int64_t pass_index,
                                                             uint64_t *moves) {
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t tiles = rows_total / 64;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+  const int l = threadIdx.x & 63;
+  const TileRange tr = wave_tiles(rows_total / 64, 4);
+  for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     CellRow cr;
-    load_cell_row(T, St, tile, l, phase, cr);
+    load_row(T, St, tile_system(T, tile, phase), tile, l, cr);
     int dE = 0;
     bool changed = false;
     if (cr.valid) {

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -315,6 +316,7 @@ int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &out) {
       for (int32_t p = out.n_phases; p < 5; ++p) out.pc[p] = (int32_t)out.cells.size();
       // cell records: the neighbours outside the cell, by direction and bit
       out.cellrec.assign((size_t)L * L * kCellRecWords, 0u);
+      out.cell_fast = 1;
       for (int32_t c = 0; c < L * L; ++c) {
         uint32_t *rec = out.cellrec.data() + (size_t)c * kCellRecWords;
         for (int32_t k = 0; k < 8; ++k) {
@@ -326,6 +328,8 @@ int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &out) {
             const uint32_t ent = (uint32_t)(uint8_t)t.J[j] | ((uint32_t)(8 * dir + (nb & 7)) << 8);
             rec[2 * k + (e >> 1)] |= ent << (16 * (e & 1));
             ++e;
+            if ((nb & 7) != k) out.cell_fast = 0;
+            rec[24 + k] |= (uint32_t)(uint8_t)(int8_t)(2 * t.J[j]) << (8 * dir);
           }
           rec[16 + (k >> 2)] |= (uint32_t)(uint8_t)t.h << (8 * (k & 3));
           rec[18 + (k >> 2)] |= (uint32_t)(uint8_t)t.Jtau << (8 * (k & 3));
@@ -476,6 +480,7 @@ int32_t plan(const std::vector<SysHost> &hs, GraphPlan &g) {
     si.fifo_words = h.FW;
     si.cb0 = (int32_t)cb;
     si.grid_L = h.grid_L;
+    si.cell_fast = h.cell_fast;
     si.n_phases = h.n_phases;
     si.cl0 = (int32_t)cl;
     for (int p = 0; p < 5; ++p) si.pc[p] = h.pc[p];
@@ -553,10 +558,38 @@ int32_t plan(const std::vector<SysHost> &hs, GraphPlan &g) {
     int32_t rc = shape_bucket(b, tpw, G, Kmax);
     if (rc) return rc;
     tile_bucket(g, b, kv.second);
+    int64_t attempts = 0;
+    for (int32_t s : kv.second) attempts += (int64_t)g.sys[s].K * g.sys[s].S * g.sys[s].M;
     g.buckets.push_back(b);
     g.bucket_sys.push_back(kv.second);
+    g.bucket_cost.push_back(attempts);
   }
+  assign_streams(g, hw_queues());
   return ISING_OK;
+}
+
+void assign_streams(GraphPlan &g, int32_t max_streams) {
+  const int32_t nb = (int32_t)g.buckets.size();
+  g.n_streams = std::max(1, std::min(nb, max_streams));
+  g.launch_order.resize(nb);
+  for (int32_t b = 0; b < nb; ++b) g.launch_order[b] = b;
+  std::stable_sort(g.launch_order.begin(), g.launch_order.end(),
+                   [&](int32_t a, int32_t b) { return g.bucket_cost[a] > g.bucket_cost[b]; });
+  std::vector<int64_t> load(g.n_streams, 0);
+  g.stream_of.assign(nb, 0);
+  for (int32_t b : g.launch_order) {
+    int32_t best = 0;
+    for (int32_t q = 1; q < g.n_streams; ++q)
+      if (load[q] < load[best]) best = q;
+    g.stream_of[b] = best;
+    load[best] += g.bucket_cost[b];
+  }
+}
+
+int32_t hw_queues() {
+  const char *v = getenv("GPU_MAX_HW_QUEUES");
+  int32_t n = v ? atoi(v) : 4;
+  return n < 1 ? 4 : (n > 8 ? 8 : n);
 }
 
 int32_t build_all(const ising_system_desc *sys, int32_t n_sys, std::vector<SysHost> &hs) {

@@ -21,6 +21,7 @@ struct SysHost {
   int32_t S, M, ring, F, deg, dmax, K, cell, FW;
   int32_t ds = 0, dt = 0;  // two-field bounds: max |h| + sum |J in-slice|, max sum |J_tau| of a spin
   int32_t grid_L = 0, n_phases = 0;
+  int32_t cell_fast = 0;  // cell records carry couplings by direction (every outside neighbour of spin k is spin k)
   std::vector<uint16_t> cells;  // cell indices, phase by phase
   int32_t pc[5] = {0, 0, 0, 0, 0};
   std::vector<TmplSpin> tmpl;
@@ -67,6 +68,17 @@ struct GraphPlan {
   uint32_t pair_classes = 0;
   std::string pair_why;
   std::vector<double> qa, qc;  // per slot, while the two-field form is on
+  // Streams of a sweep with several buckets.  HIP maps a process's streams onto
+  // a few hardware queues (GPU_MAX_HW_QUEUES, 4 by default), and the kernels of
+  // one queue run one after another, so a sweep uses at most that many streams
+  // (stream 0 is the caller's): bucket b runs on stream_of[b], the buckets are
+  // enqueued in launch_order (largest cost first), and the buckets are spread
+  // over the streams largest first onto the least loaded one.  bucket_cost[b]
+  // is the bucket's time per sweep as the autotuner measured it, else its
+  // attempts per sweep.
+  std::vector<int64_t> bucket_cost;
+  std::vector<int32_t> stream_of, launch_order;
+  int32_t n_streams = 1;
   // LDS words of a walker slot for system s in the current form
   int32_t walker_words(int32_t s) const {
     const SysInfo &si = sys[s];
@@ -91,6 +103,11 @@ void tile_bucket(GraphPlan &g, Bucket &b, const std::vector<int32_t> &systems);
 void retile(GraphPlan &g);
 // Systems, slots, buckets and default shapes of a batch of packed systems.
 int32_t plan(const std::vector<SysHost> &hs, GraphPlan &g);
+// Spread the buckets over at most max_streams streams by their bucket_cost
+// (largest first, each onto the stream with the least cost so far).
+void assign_streams(GraphPlan &g, int32_t max_streams);
+// Hardware queues a process gets (GPU_MAX_HW_QUEUES, else HIP's default of 4; 1..8).
+int32_t hw_queues();
 
 // Most sweeps one launch of the sweep kernel (bucket b, its current shape) may
 // run: its per-launch 32-bit counters (flips, wavefront steps and steps with a

@@ -39,6 +39,8 @@ struct SysInfo {
   int32_t pc[5];           // phase p owns cell-list entries [pc[p], pc[p+1])
   int32_t rows;            // proposal work rows per walker (largest phase)
   int32_t pl0;             // layer-pair order: first generator lane of walker 0 (M/2 per walker)
+  int32_t cell_fast;       // 1: every outside in-slice neighbour of cell spin k is spin k of its cell
+                           // (K4,4 grids): cell records then carry couplings by direction
   int64_t row0;            // first proposal work row of walker 0
   int64_t cell0;           // global index of walker 0's cell 0 (cells numbered walker-major)
 };
@@ -63,8 +65,11 @@ static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
 //                 << 8) | (left << 16) | (right << 24);
 //   [16], [17]    h_k as int8, k = 0..3 and 4..7;
 //   [18], [19]    J_tau of spin k as int8;
-//   [20 + k]      2J of spin k (< 4) to the spins 4 + i of the cell, byte i.
-constexpr int kCellRecWords = 24;
+//   [20 + k]      2J of spin k (< 4) to the spins 4 + i of the cell, byte i;
+//   [24 + k]      when the system's cell_fast is set: 2J of spin k to spin k of
+//                 the cell above, below, left and right, bytes 0..3 (0 where
+//                 there is none), matching the byte order of the word above.
+constexpr int kCellRecWords = 32;
 
 // One workgroup of the sweep: `nw` walkers of system `sys` starting at `w0`.
 struct Tile {

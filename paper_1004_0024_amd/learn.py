@@ -102,11 +102,25 @@ def ess_summary(graph, series, burn=0.2):
     return {"coldest_total": float(np.sum(coldest)), "median_slot": float(np.median(allv))}
 
 
+def slot_ess_totals(graph, series, positions, burn=0.2):
+    """ESS of the energy at ladder position k (0 = hottest), summed over systems, for
+    every k in `positions` (systems with fewer slots are skipped)."""
+    tot = {int(k): 0.0 for k in positions}
+    base = 0
+    for s in graph.systems:
+        K = len(s.beta)
+        for k in tot:
+            if k < K:
+                tot[k] += _ess.ess(series[:, base + k], burn)
+        base += K
+    return tot
+
+
 def compare_means(graph, series_a, series_b, burn=0.2):
     """Slot mean energies of two chains on the same systems, in units of their combined
     standard error (variance / ESS per series).  Returns, per slot position in the ladder
-    (0 = hottest), the median |z| over systems, and the fraction of (system, slot) pairs
-    with |z| < 4."""
+    (0 = hottest), the median |z| over systems and the fraction of systems with |z| < 4,
+    and the fraction of all (system, slot) pairs with |z| < 4."""
     zs = []
     base = 0
     for s in graph.systems:
@@ -122,4 +136,17 @@ def compare_means(graph, series_a, series_b, burn=0.2):
         base += K
     zs = np.abs(np.array(zs))
     return {"median_abs_z_by_slot": [float(v) for v in np.median(zs, axis=0)],
+            "frac_below_4_by_slot": [float(v) for v in np.mean(zs < 4.0, axis=0)],
             "frac_abs_z_below_4": float(np.mean(zs < 4.0))}
+
+
+def matched_slots(graph, series, reference="plain", burn=0.2, frac=0.99):
+    """Ladder positions where every chain's slot means agree with the reference chain's:
+    |z| < 4 (compare_means) for at least `frac` of the systems, for each chain of
+    `series` (a dict of [steps, slots] energy series).  Returns (positions, per-chain
+    comparisons)."""
+    comp = {name: compare_means(graph, e, series[reference], burn)
+            for name, e in series.items() if name != reference}
+    K = min(len(s.beta) for s in graph.systems)
+    ok = [k for k in range(K) if all(c["frac_below_4_by_slot"][k] >= frac for c in comp.values())]
+    return ok, comp

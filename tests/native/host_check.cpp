@@ -139,8 +139,27 @@ static void check_batch(const char *name, const std::vector<Sys> &systems) {
     g.buckets[bi] = orig;
   }
   retile(g);
-  printf("%s systems %zu bytes %zu buckets %zu shapes %d sweep_limit %lld pairs_limit %lld\n", name,
-         systems.size(), bytes, g.buckets.size(), shapes, (long long)default_limit,
+  // streams: every bucket on one of at most hw_queues() streams, the launch
+  // order a permutation by descending cost, and each bucket, largest first,
+  // placed on a stream with the least cost so far
+  CHECK(g.n_streams >= 1 && g.n_streams <= 8 && g.n_streams <= (int32_t)g.buckets.size());
+  {
+    std::vector<int64_t> load(g.n_streams, 0);
+    std::vector<int> seen_b(g.buckets.size(), 0);
+    for (size_t i = 0; i < g.launch_order.size(); ++i) {
+      const int32_t b = g.launch_order[i];
+      CHECK(b >= 0 && b < (int32_t)g.buckets.size() && !seen_b[b]);
+      seen_b[b] = 1;
+      if (i) CHECK(g.bucket_cost[g.launch_order[i - 1]] >= g.bucket_cost[b]);
+      CHECK(g.stream_of[b] >= 0 && g.stream_of[b] < g.n_streams);
+      int64_t lo = load[0];
+      for (int64_t v : load) lo = std::min(lo, v);
+      CHECK(load[g.stream_of[b]] == lo);  // placed on a least loaded stream
+      load[g.stream_of[b]] += g.bucket_cost[b];
+    }
+  }
+  printf("%s systems %zu bytes %zu buckets %zu streams %d shapes %d sweep_limit %lld pairs_limit %lld\n", name,
+         systems.size(), bytes, g.buckets.size(), g.n_streams, shapes, (long long)default_limit,
          (long long)pairs_sweep_limit(g));
 }
 

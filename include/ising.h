@@ -117,16 +117,18 @@ int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row
 
 /* Launch shapes.  Systems with the same template size and kernel variant
  * form a bucket, swept by one launch.  A walker's template columns are spread
- * over `tpw` threads (a power of two; a thread visits ceil(S/tpw) <= 8
- * columns per level; tpw <= 64 keeps a walker inside one wavefront) and a
- * workgroup holds `walkers_per_group` walkers.  Shapes change speed only: the
+ * over `tpw` threads (a power of two up to 64, which keeps a walker inside one
+ * wavefront, or any count from 65 to 1024, walkers back to back; a thread
+ * visits ceil(S/tpw) <= 8 columns per level) and a workgroup holds
+ * `walkers_per_group` walkers.  Shapes change speed only: the
  * chain is the same for every shape.  bucket_info writes, in this order:
  *   S, systems, walkers, attempts per sweep, tpw, walkers per group, columns
  *   per thread, workgroup threads, LDS bytes per workgroup, workgroups, ladder
  *   (1 when every workgroup holds whole systems, at most 64 threads per walker,
  *   and the swap state fits: then, when every bucket is a ladder bucket,
  *   ising_sweep runs the swap rounds inside the sweep kernel, one launch per
- *   call; the chain is the same).
+ *   call; the chain is the same), stream (0 = the caller's; see below), work
+ *   (attempts per sweep, or nanoseconds per sweep once autotuned).
  * set_launch returns ISING_E_RANGE for a shape that does not fit (threads,
  * LDS, columns per thread) and leaves the bucket unchanged.
  * With several buckets a sweep forks side streams (default priority) from the
@@ -187,10 +189,15 @@ int32_t ising_state_sizes(const ising_graph *g, int64_t *counts);
 int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *walker_seeds,
                          const uint32_t *swap_seeds, void *stream);
 
-/* n_sweeps sweeps of every walker; after each sweep whose running count is a
- * multiple of swap_every (> 0; 0 = never) one swap round of every system.
- * e_series (device, nullable): [n_sweeps][slots] energy of the walker at each
- * slot after each sweep and its swap round.                                  */
+/* n_sweeps sweeps of every walker (Figure 1: spins in ascending index order,
+ * one uniform each, a flip when it falls below the flip probability, the
+ * neighbours' local fields then current as in Figures 3 and 6); after each
+ * sweep whose running count is a multiple of swap_every (> 0; 0 = never) one
+ * swap round of every system (replica exchange, Section 1).  Long calls run as
+ * several launches whose 32-bit per-launch counters cannot wrap; the chain is
+ * the same.  e_series (device, nullable): [n_sweeps][slots] energy of the
+ * walker at each slot after each sweep and its swap round.  ISING_E_INVAL for
+ * negative counts, ISING_E_STATE before ising_init_state.                    */
 int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,
                     int32_t *e_series, void *stream);
 
@@ -209,7 +216,8 @@ int32_t ising_replay_launch(ising_replay *r, ising_state *st, void *stream);
 void ising_replay_free(ising_replay *r);
 
 /* Autotuner: for every bucket, time each admissible launch shape (tpw a power
- * of two, walkers per group 1, 2, 4 .. 32) with HIP events over `reps`
+ * of two from 8 to 1024, or above 64 the template size S, ceil(S/2) and their
+ * multiples of 64; walkers per group 1, 2, 4 .. 32) with HIP events over `reps`
  * single-sweep launches on `scratch` (an initialised state of this graph whose
  * chain it advances), then keep the fastest shape.  Optionally writes one row
  * {bucket, tpw, walkers_per_group, nanoseconds per sweep} per trial to
@@ -223,7 +231,9 @@ int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t reps, void 
                        int32_t report_rows);
 
 /* One swap round of every system with the given parity (0: pairs (0,1),(2,3)..;
- * 1: (1,2),(3,4)..).  Does not change st->rounds.                             */
+ * 1: (1,2),(3,4)..): parallel tempering (Section 1) with the rule and draw
+ * order stated at the top of this file, FP64 on the device, near-threshold
+ * decisions counted in st->swap_near.  Does not change st->rounds.           */
 int32_t pt_swap(const ising_graph *g, ising_state *st, int32_t parity, void *stream);
 
 /* e_row[slots] (device) = running energy of the walker at each slot. */
@@ -234,8 +244,10 @@ int32_t ising_record_slots(const ising_graph *g, const ising_state *st, int32_t 
 int32_t ising_stats(const ising_graph *g, const ising_state *st, uint64_t *out, void *stream);
 
 /* Observables per walker into device int32 obs[R][6]: cost recomputed from the
- * spins, magnetisation sum_i s_i, running cost, temperature slot, tau-bond sum
- * B recomputed from the spins, running B.                                     */
+ * spins (the cost function f of Section 1), magnetisation sum_i s_i, running
+ * cost, temperature slot, tau-bond sum B recomputed from the spins (the tau
+ * edges of the layered models, Section 3.1), running B.  obs is caller-owned,
+ * R = walkers of the graph; ISING_E_INVAL for a NULL pointer.                */
 int32_t ising_observables(const ising_graph *g, const ising_state *st, int32_t *obs, void *stream);
 /* Recompute every walker's running cost and tau-bond sum from its spins. */
 int32_t ising_refresh_energies(const ising_graph *g, ising_state *st, void *stream);

@@ -208,13 +208,15 @@ class Graph:
     def handle(self):
         return self._handle
 
-    _BUCKET_KEYS = ["S", "systems", "walkers", "attempts", "tpw", "G", "cpt", "threads", "lds", "tiles", "ladder"]
+    _BUCKET_KEYS = ["S", "systems", "walkers", "attempts", "tpw", "G", "cpt", "threads", "lds", "tiles", "ladder",
+                    "stream", "work"]
 
     def buckets(self):
         out = []
+        n = len(self._BUCKET_KEYS)
         for b in range(lib().ising_n_buckets(self._handle)):
-            v = np.zeros(11, np.int64)
-            _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), 11))
+            v = np.zeros(n, np.int64)
+            _check(lib().ising_bucket_info(self._handle, b, _np_ptr(v), n))
             out.append(dict(zip(self._BUCKET_KEYS, (int(x) for x in v))))
         return out
 

@@ -280,9 +280,10 @@ extern "C" int32_t ising_bucket_info(const ising_graph *g, int32_t bucket, int64
     walkers += g->sys[s].K;
     attempts += (int64_t)g->sys[s].K * g->sys[s].S * g->sys[s].M;
   }
-  const int64_t v[11] = {b.S, (int64_t)g->bucket_sys[bucket].size(), walkers, attempts, b.tpw, b.G,
-                         b.cpt, b.threads, (int64_t)b.lds, b.ntiles, b.ladder};
-  for (int32_t i = 0; i < n && i < 11; ++i) out[i] = v[i];
+  const int64_t v[13] = {b.S, (int64_t)g->bucket_sys[bucket].size(), walkers, attempts, b.tpw, b.G,
+                         b.cpt, b.threads, (int64_t)b.lds, b.ntiles, b.ladder, g->stream_of[bucket],
+                         g->bucket_cost[bucket]};
+  for (int32_t i = 0; i < n && i < 13; ++i) out[i] = v[i];
   return ISING_OK;
 }
 
@@ -530,7 +531,8 @@ extern "C" void ising_replay_free(ising_replay *r) {
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: time every admissible launch shape of every bucket on a scratch
+// Autotuner: time every admissible launch shape of every bucket (threads per
+// walker from tpw_candidates, 1 to 32 walkers per workgroup) on a scratch
 // state (single-sweep launches, as in a swap-every-sweep loop) and keep the
 // fastest; the kept shapes' times then spread the buckets over the streams.
 // The chain does not depend on the shape.
@@ -559,7 +561,7 @@ extern "C" int32_t ising_autotune(ising_graph *g, ising_state *scratch, int32_t 
     const Bucket orig = g->buckets[bi];
     Bucket best = orig;
     int64_t best_ns = -1;
-    for (int32_t tpw = 8; tpw <= 1024; tpw <<= 1) {
+    for (int32_t tpw : tpw_candidates(orig.S)) {
       for (int32_t G = 1; G <= 32; G <<= 1) {
         Bucket b = orig;
         if (shape_bucket(b, tpw, G, Kmax, !g->two_field) != ISING_OK || b.G != G) continue;

@@ -398,10 +398,12 @@ Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles,
   return L;
 }
 
-// Launch shape of a bucket: `tpw` threads per walker (a power of two; each
-// thread owns ceil(S/tpw) <= 8 columns) and G walkers per workgroup.
+// Launch shape of a bucket: `tpw` threads per walker (a power of two up to 64,
+// or any count from 65 to 1024; each thread owns ceil(S/tpw) <= 8 columns) and
+// G walkers per workgroup.
 int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax, bool allow_ladder) {
-  if (tpw < 1 || (tpw & (tpw - 1)) != 0 || tpw > 1024) return fail(ISING_E_RANGE, "tpw must be a power of two <= 1024");
+  if (tpw < 1 || tpw > 1024 || (tpw <= 64 && (tpw & (tpw - 1)) != 0))
+    return fail(ISING_E_RANGE, "tpw must be a power of two up to 64, or 65..1024");
   const int32_t need = (b.S + tpw - 1) / tpw;
   int32_t cpt = 1;
   while (cpt < need) cpt <<= 1;
@@ -447,6 +449,19 @@ void tile_bucket(GraphPlan &g, Bucket &b, const std::vector<int32_t> &systems) {
     for (int32_t w0 = 0; w0 < g.sys[s].K; w0 += b.G)
       g.tiles.push_back(Tile{s, w0, std::min(b.G, g.sys[s].K - w0), 0});
   b.ntiles = (int32_t)g.tiles.size() - b.tile0;
+}
+
+std::vector<int32_t> tpw_candidates(int32_t S) {
+  std::vector<int32_t> v;
+  for (int32_t t = 8; t <= 1024; t <<= 1) v.push_back(t);
+  for (int32_t t : {S, (S + 1) / 2})
+    if (t > 64 && t <= 1024) {
+      v.push_back(t);
+      v.push_back(std::min(1024, (t + 63) / 64 * 64));
+    }
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
 }
 
 void retile(GraphPlan &g) {
@@ -604,10 +619,11 @@ int32_t build_all(const ising_system_desc *sys, int32_t n_sys, std::vector<SysHo
 
 
 // Per sweep, a walker of system s in bucket b adds at most: N = S M flips;
-// max(1, tpw / 64) wavefronts x cpt columns x (M + F - 1) levels wavefront
-// steps (a wavefront's steps go to the walker of its first lane; when tpw < 64
-// that walker takes the steps of the wavefront's other walkers too, at most
-// one per column slot and level); and a lane's |2 sum d| grows by at most
+// (ceil(tpw / 64) + 1) wavefronts x cpt columns x (M + F - 1) levels wavefront
+// steps (a wavefront's steps go to the walker of its first lane, and the
+// wavefronts whose first lane is one of a walker's are at most that many; when
+// tpw < 64 that walker takes the steps of the wavefront's other walkers too, at
+// most one per column slot and level); and a lane's |2 sum d| grows by at most
 // 2 * 63 * cpt * M.  A pair's acceptances grow by at most one per sweep.
 int64_t bucket_sweep_limit(const GraphPlan &g, size_t b) {
   const Bucket &bk = g.buckets[b];
@@ -615,7 +631,7 @@ int64_t bucket_sweep_limit(const GraphPlan &g, size_t b) {
   for (int32_t s : g.bucket_sys[b]) {
     const SysInfo &si = g.sys[s];
     const int64_t N = (int64_t)si.S * si.M;
-    const int64_t waves = std::max<int64_t>(1, bk.tpw / 64);
+    const int64_t waves = (bk.tpw + 63) / 64 + 1;
     const int64_t steps = waves * bk.cpt * (int64_t)(si.M + si.F - 1);
     const int64_t dsum = 2 * 63 * (int64_t)bk.cpt * si.M;
     lim = std::min(lim, (int64_t)UINT32_MAX / std::max(N, steps));

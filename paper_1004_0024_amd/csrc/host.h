@@ -98,6 +98,11 @@ Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles,
 // default shape of a template size.
 int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax, bool allow_ladder = true);
 void default_shape(int32_t S, int32_t walker_words, int32_t Kmax, int32_t &tpw, int32_t &G, bool allow_ladder = true);
+// Threads per walker the autotuner tries for a template of S spins: the powers
+// of two from 8 to 1024, and above 64 the counts that leave few idle lanes:
+// S and ceil(S / 2) (one or two columns per thread, walkers back to back) and
+// their multiples of 64.
+std::vector<int32_t> tpw_candidates(int32_t S);
 // Tiles of a bucket appended to g.tiles; all buckets' tiles rebuilt in order.
 void tile_bucket(GraphPlan &g, Bucket &b, const std::vector<int32_t> &systems);
 void retile(GraphPlan &g);

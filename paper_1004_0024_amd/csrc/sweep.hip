@@ -20,9 +20,12 @@
 // positions c*TPW + t, c < CPT, and visits them one after another inside a
 // level (independent attempts, so their latencies overlap).  Lane positions
 // hold the columns in order of their level offset, so the columns of a
-// wavefront start (and end) within few levels of each other.  When TPW <= 64 a
-// walker lives inside one wavefront and a level ends with a wavefront fence
-// instead of a workgroup barrier.
+// wavefront start (and end) within few levels of each other.  TPW is a power of
+// two up to 64, or any count above 64.  When TPW <= 64 a walker lives inside
+// one wavefront and a level ends with a wavefront fence instead of a workgroup
+// barrier; above 64 the walkers of a workgroup lie back to back, so with TPW
+// not a multiple of 64 a wavefront can hold the end of one walker and the
+// start of the next.
 //
 // Data in LDS for the whole launch, per walker:
 //  - spins, one bit each, slice rows of RS words (RS odd when > 1, so rows of
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
   } else {
     const int levels = M + F - 1;
-    const bool wave_walker = !WS || TPW >= 64;  // a wavefront's lanes belong to one walker
+    const bool wave_walker = (TPW & 63) == 0;  // every wavefront's lanes belong to one walker
     for (int sw = 0; sw < n_sweeps; ++sw) {
       const int chunk0 = sw * M;
       for (int lv = 0; lv < levels; ++lv) {

@@ -140,13 +140,18 @@ def compare_means(graph, series_a, series_b, burn=0.2):
             "frac_abs_z_below_4": float(np.mean(zs < 4.0))}
 
 
-def matched_slots(graph, series, reference="plain", burn=0.2, frac=0.99):
+def matched_slots(graph, series, reference="plain", null=None, burn=0.2, frac=0.99):
     """Ladder positions where every chain's slot means agree with the reference chain's:
     |z| < 4 (compare_means) for at least `frac` of the systems, for each chain of
-    `series` (a dict of [steps, slots] energy series).  Returns (positions, per-chain
-    comparisons)."""
+    `series` (a dict of [steps, slots] energy series).  With `null` (the name of a later,
+    independent stretch of the reference chain) a position also counts when every chain
+    agrees with the reference at least as often as that stretch does: the reference
+    against itself calibrates the test where the standard errors are loose.  Returns
+    (positions, comparisons by chain name, the null's included)."""
     comp = {name: compare_means(graph, e, series[reference], burn)
             for name, e in series.items() if name != reference}
     K = min(len(s.beta) for s in graph.systems)
-    ok = [k for k in range(K) if all(c["frac_below_4_by_slot"][k] >= frac for c in comp.values())]
+    chains = [c for name, c in comp.items() if name != null]
+    bar = [frac if null is None else min(frac, comp[null]["frac_below_4_by_slot"][k]) for k in range(K)]
+    ok = [k for k in range(K) if all(c["frac_below_4_by_slot"][k] >= bar[k] for c in chains)]
     return ok, comp

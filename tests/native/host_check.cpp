@@ -116,10 +116,16 @@ static void check_batch(const char *name, const std::vector<Sys> &systems) {
     int32_t Kmax = 1;
     for (int32_t s : g.bucket_sys[bi]) Kmax = std::max(Kmax, g.sys[s].K);
     const Bucket orig = g.buckets[bi];
-    for (int32_t tpw = 1; tpw <= 2048; tpw <<= 1)
+    std::vector<int32_t> tpws = tpw_candidates(orig.S);
+    for (int32_t t : {1, 2, 4, 2048, 63, 65, 100, 1025}) tpws.push_back(t);  // also invalid ones
+    for (int32_t tpw : tpws)
       for (int32_t G = 1; G <= 64; G <<= 1) {
         Bucket b = orig;
-        if (shape_bucket(b, tpw, G, Kmax, true) != ISING_OK) continue;
+        if (shape_bucket(b, tpw, G, Kmax, true) != ISING_OK) {
+          CHECK(tpw > 1024 || (tpw <= 64 && (tpw & (tpw - 1))) || b.S > tpw * 8 || G * tpw > 1024 ||
+                (size_t)G * b.walker_words * 4 > 160 * 1024);
+          continue;
+        }
         CHECK(b.cpt >= 1 && b.cpt <= 8 && (int64_t)b.tpw * b.cpt >= b.S);
         CHECK(b.threads % 64 == 0 && b.threads <= 1024 && b.lds <= 160 * 1024);
         g.buckets[bi] = b;

@@ -59,3 +59,36 @@ def test_buckets_spread_over_streams_keep_the_chain():
         ch.sweeps(4, 1)
     for s, ch in enumerate(chains):
         compare_system(st, s, ch, "time-weighted streams, captured")
+
+
+@pytest.mark.parametrize("L,M,K,tpw,G", [
+    (3, 6, 8, 72, 8),     # 72-spin walkers back to back: 9 wavefronts, walkers straddle them
+    (3, 6, 8, 72, 3),     # 216 threads: the last wavefront partly idle
+    (3, 6, 5, 128, 2),    # a multiple of 64 above S
+    (5, 5, 5, 200, 4),
+    (6, 4, 4, 288, 2),
+    (6, 4, 4, 320, 1),
+    (6, 4, 4, 144, 3),    # ceil(S / 2): two columns per thread
+    (7, 4, 3, 196, 2),
+    (8, 3, 2, 576, 1),    # more threads than spins
+])
+def test_threads_per_walker_not_a_power_of_two(L, M, K, tpw, G):
+    """Shapes with a thread count per walker above 64 that is not a power of two keep the
+    chain, the MT windows and every counter (flips are counted per lane when a wavefront
+    holds two walkers) bit for bit; swap rounds after single sweeps and a 7-sweep launch."""
+    wl = Workload(f"tpw {tpw} G {G}", [make_chimera_system(L, M, 800 + L, K)], 0, 1)
+    g, st = make_state(wl)
+    g.set_launch(0, tpw, G)
+    b = g.buckets()[0]
+    say("shape", {k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds")})
+    assert (b["tpw"], b["G"]) == (tpw, min(G, K))
+    ch = chains_for(wl, [0])[0]
+    st.sweep(3, 1)
+    ch.sweeps(3, 1)
+    compare_system(st, 0, ch, "single sweeps")
+    st.sweep(7, 0)
+    ch.sweeps(7, 0)
+    compare_system(st, 0, ch, "7-sweep launch")
+    st.sweep(2, 1)
+    ch.sweeps(2, 1)
+    compare_system(st, 0, ch, "after")

@@ -309,11 +309,11 @@ __device__ __forceinline__ void add_cell_moves(const DevState &St, uint64_t *mov
 // ---- one colour class of cell moves in one launch -----------------------------
 // Each wavefront takes tiles of 64 rows (row = walker x cell of the class, one
 // lane per row): the lane computes its cell's boundary fields and writes the
-// BF16 network input to LDS; the three layers run on 16x16x32 BF16 matrix
-// cores with the rows as the N side (four 16-row tiles), so that a layer's
-// results stay in the lanes that feed them to the next layer; the logits go
-// back through LDS to the row's lane, which draws the proposal and takes the
-// Metropolis-Hastings decision.
+// BF16 network input to LDS; the three layers run on BF16 matrix cores with the
+// rows as the N side (16-row tiles), so that a layer's results stay in the
+// lanes that feed them to the next layer; the logits go back through LDS to the
+// row's lane, which draws the proposal and takes the Metropolis-Hastings
+// decision.
 //
 // Result tiles: lane l holds units 4(l/16) + j (j < 4) of row l % 16.  The
 // next layer's B operand wants, in lane l, 8 consecutive positions of the
@@ -331,17 +331,7 @@ __device__ __forceinline__ int unit_at(int c) {
 
 // Row strides are padded by 8 BF16 (16 bytes): the 16 rows that one matrix
 // operand read touches then fall on distinct LDS banks.
-constexpr int kS1 = 40, kS2 = 136;
-// Wavefronts per workgroup: six share one copy of the weights (75 KB of LDS),
-// two workgroups fit a compute unit, three wavefronts per SIMD.
-constexpr int kProposeWaves = 6;
-struct alignas(16) ProposeLds {
-  uint16_t W1[128 * kS1];  // [unit][input], inputs padded to 32
-  uint16_t W2[128 * kS2];  // [unit][position], positions in unit_at order
-  uint16_t W3[16 * kS2];   // [output (8 + 8 zero rows)][position]
-  float b1[128], b2[128], b3[16];
-  uint16_t X[kProposeWaves][64 * kS1];  // per wavefront: inputs of its 64 rows, then their logits
-};
+constexpr int kS2 = 136;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -366,16 +356,42 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                   0, 0);
 }
 
-__global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_waves_per_eu(3)))
+// Occupancy: eight wavefronts per workgroup share one LDS copy of the weights
+// (69 KiB with their inputs), two workgroups per CU, four wavefronts per SIMD
+// (at most 128 VGPRs).  To fit, layer 1 takes only the 9 non-zero inputs (b/8
+// and beta; the 8 spin slots are zero) as a 16-wide contraction (16x16x16
+// MFMA; the zero inputs contributed nothing: a pass of the 32-wide form gave
+// the same spins and energies bit for bit), and the network runs on the 64
+// rows in two halves of 32, so only one half's layer-1 activations (32 VGPRs)
+// are live at a time; each half reads the layer-2 weights again.
+constexpr int kProposeWaves = 8;
+constexpr int kX2 = 24;  // input row stride (bf16): 16 positions + 8 padding
+struct alignas(16) ProposeLds {
+  uint16_t W1[128 * kX2];  // [unit][position]: b0..b7, beta, zeros
+  uint16_t W2[128 * kS2];  // [unit][position], positions in unit_at order
+  uint16_t W3[16 * kS2];   // [output (8 + 8 zero rows)][position]
+  float b1[128], b2[128], b3[16];
+  uint16_t X[kProposeWaves][64 * kX2];  // per wavefront: inputs of its 64 rows, then their logits
+};
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x4 mfma16k16(u32x2 a, u32x2 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a), __builtin_bit_cast(s16x4, b), c, 0,
+                                                   0, 0);
+}
+
+__global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_waves_per_eu(4)))
     cell_propose_kernel(DevTables T, DevState St, int32_t n_sys, int64_t rows_total, int32_t phase, const float *w,
-                        const uint16_t *wb, uint64_t key, int64_t pass_index, uint64_t *moves) {
+                         const uint16_t *wb, uint64_t key, int64_t pass_index, uint64_t *moves) {
   __shared__ ProposeLds s;
-  // 16-byte pieces: W1 rows as they are; for W2 and W3 the 8 positions (kk, g, 0..7)
-  // are units 32kk + 4g + 0..3 and 32kk + 16 + 4g + 0..3, two 8-byte pieces.
-  for (int i = threadIdx.x; i < 128 * 4; i += blockDim.x)
-    *(uint4 *)(s.W1 + (i >> 2) * kS1 + (i & 3) * 8) = *(const uint4 *)(wb + kPW1 + i * 8);
+  // W1: inputs 8..16 of the packed rows (b0..b7, beta) to positions 0..8
+  for (int i = threadIdx.x; i < 128 * kX2; i += blockDim.x) {
+    const int u = i / kX2, p = i - u * kX2;
+    s.W1[i] = p < 9 ? wb[kPW1 + u * 32 + 8 + p] : (uint16_t)0;
+  }
   for (int i = threadIdx.x; i < 144 * 16; i += blockDim.x) {
-    const int row = i >> 4, kk = (i >> 2) & 3, gg = i & 3;  // rows 0..127 of W2, then 0..15 of W3
+    const int row = i >> 4, kk = (i >> 2) & 3, gg = i & 3;
     const uint16_t *src = row < 128 ? wb + kPW2 + row * 128 : wb + kPW3 + (row - 128) * 128;
     uint16_t *dst = row < 128 ? s.W2 + row * kS2 : s.W3 + (row - 128) * kS2;
     const uint2 a = *(const uint2 *)(src + kk * 32 + 4 * gg), b = *(const uint2 *)(src + kk * 32 + 16 + 4 * gg);
@@ -390,88 +406,77 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
 
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, n16 = l & 15, g = l >> 4;
   uint16_t *X = s.X[wv];
-  const TileRange tr = wave_tiles(rows_total / 64, kProposeWaves);  // rows_total is a multiple of 64
+  float *Lg = (float *)X;
+  const TileRange tr = wave_tiles(rows_total / 64, kProposeWaves);
   for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
-    // ---- this lane's row: locate the cell, boundary fields, input ----
     CellRow cr;
     load_row(T, St, tile_system(T, tile, phase), tile, l, cr);
     const bool valid = cr.valid;
     const int *b = cr.b;
     const float beta = cr.beta;
     {
-      u32x4 *xr = (u32x4 *)(X + l * kS1);
-      const u32x4 zero = {0u, 0u, 0u, 0u};
-      xr[0] = zero;
-      xr[1] = u32x4{pack_bf2(b[0] * 0.125f, b[1] * 0.125f), pack_bf2(b[2] * 0.125f, b[3] * 0.125f),
+      u32x4 *xr = (u32x4 *)(X + l * kX2);
+      xr[0] = u32x4{pack_bf2(b[0] * 0.125f, b[1] * 0.125f), pack_bf2(b[2] * 0.125f, b[3] * 0.125f),
                     pack_bf2(b[4] * 0.125f, b[5] * 0.125f), pack_bf2(b[6] * 0.125f, b[7] * 0.125f)};
-      xr[2] = u32x4{(uint32_t)f2bf(beta), 0u, 0u, 0u};
-      xr[3] = zero;
+      xr[1] = u32x4{(uint32_t)f2bf(beta), 0u, 0u, 0u};
     }
     wave_fence();
-
-    // ---- layer 1: 8 unit tiles x 4 row tiles ----
-    u32x4 xb[4];
+    const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));
 #pragma unroll
-    for (int t = 0; t < 4; ++t) xb[t] = *(const u32x4 *)(X + (t * 16 + n16) * kS1 + g * 8);
-    u32x4 h1[4][4];
-    u32x4 w1f[8];
+    for (int half = 0; half < 2; ++half) {
+      u32x2 xb[2];
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) w1f[ft] = *(const u32x4 *)(s.W1 + (ft * 16 + n16) * kS1 + g * 8);
+      for (int tt = 0; tt < 2; ++tt) xb[tt] = *(const u32x2 *)(X + ((2 * half + tt) * 16 + n16) * kX2 + g * 4);
+      u32x4 h1[4][2];
 #pragma unroll
-    for (int ft = 0; ft < 8; ++ft) {
-      const u32x4 a = w1f[ft];
-      const f32x4 bias = *(const f32x4 *)(s.b1 + ft * 16 + 4 * g);  // bias enters as the initial sum
+      for (int ft = 0; ft < 8; ++ft) {
+        const u32x2 a = *(const u32x2 *)(s.W1 + (ft * 16 + n16) * kX2 + g * 4);
+        const f32x4 bias = *(const f32x4 *)(s.b1 + ft * 16 + 4 * g);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const f32x4 acc = mfma16(a, xb[t], bias);
-        h1[ft >> 1][t][(ft & 1) * 2] = relu_bf2(acc[0], acc[1]);
-        h1[ft >> 1][t][(ft & 1) * 2 + 1] = relu_bf2(acc[2], acc[3]);
-      }
-    }
-    // ---- layers 2 and 3: each pair of layer-2 unit tiles (2kk, 2kk + 1) completes
-    // contraction chunk kk of layer 3, which is consumed at once ----
-    f32x4 acc3[4];
-    const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));  // outputs 8..15 are zero padding
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc3[t] = bias3;
-#pragma unroll
-    for (int kk3 = 0; kk3 < 4; ++kk3) {
-      u32x4 h2[4];
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int ft = 2 * kk3 + half;
-        u32x4 wa[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) wa[kk] = *(const u32x4 *)(s.W2 + (ft * 16 + n16) * kS2 + kk * 32 + g * 8);
-        f32x4 acc[4];
-        const f32x4 bias = *(const f32x4 *)(s.b2 + ft * 16 + 4 * g);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = bias;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) acc[t] = mfma16(wa[kk], h1[kk][t], acc[t]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          h2[t][half * 2] = relu_bf2(acc[t][0], acc[t][1]);
-          h2[t][half * 2 + 1] = relu_bf2(acc[t][2], acc[t][3]);
+        for (int tt = 0; tt < 2; ++tt) {
+          const f32x4 acc = mfma16k16(a, xb[tt], bias);
+          h1[ft >> 1][tt][(ft & 1) * 2] = relu_bf2(acc[0], acc[1]);
+          h1[ft >> 1][tt][(ft & 1) * 2 + 1] = relu_bf2(acc[2], acc[3]);
         }
       }
-      const u32x4 a3 = *(const u32x4 *)(s.W3 + n16 * kS2 + kk3 * 32 + g * 8);
+      f32x4 acc3[2] = {bias3, bias3};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc3[t] = mfma16(a3, h2[t], acc3[t]);
-    }
-    wave_fence();  // every lane has read its inputs: the region now takes logits
-    float *Lg = (float *)X;
-    if (g < 2) {
+      for (int kk3 = 0; kk3 < 4; ++kk3) {
+        u32x4 h2[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+        for (int hf = 0; hf < 2; ++hf) {
+          const int ft = 2 * kk3 + hf;
+          u32x4 wa[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Lg[(t * 16 + n16) * 8 + 4 * g + j] = acc3[t][j];
+          for (int kk = 0; kk < 4; ++kk) wa[kk] = *(const u32x4 *)(s.W2 + (ft * 16 + n16) * kS2 + kk * 32 + g * 8);
+          const f32x4 bias = *(const f32x4 *)(s.b2 + ft * 16 + 4 * g);
+          f32x4 acc[2] = {bias, bias};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(wa[kk], h1[kk][tt], acc[tt]);
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt) {
+            h2[tt][hf * 2] = relu_bf2(acc[tt][0], acc[tt][1]);
+            h2[tt][hf * 2 + 1] = relu_bf2(acc[tt][2], acc[tt][3]);
+          }
+        }
+        const u32x4 a3 = *(const u32x4 *)(s.W3 + n16 * kS2 + kk3 * 32 + g * 8);
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) acc3[tt] = mfma16(a3, h2[tt], acc3[tt]);
+      }
+      // this half's logits: rows 32 half .. 32 half + 31 take bytes 1 KB half of the region,
+      // which only holds inputs of rows already read (rows below 22 (half 0) or 43 (half 1))
+      wave_fence();
+      if (g < 2) {
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) Lg[((2 * half + tt) * 16 + n16) * 8 + 4 * g + j] = acc3[tt][j];
+      }
     }
     wave_fence();
 
-    // ---- proposal and Metropolis-Hastings test of this lane's cell ----
     int dE = 0;
     bool accept = false;
     if (valid) {
@@ -489,14 +494,12 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
         for (int q = 0; q < 4; ++q) wd[4 * blk + q] = c4[q];
       }
       uint32_t nb = 0;
-      float lratio = 0.f;  // log q(current) - log q(proposed)
+      float lratio = 0.f;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        // u < sigmoid(l)  <=>  u (1 + e^-l) < 1 (hardware exponential, FP32)
         const float u = (float)wd[k] * 0x1p-32f;
         const bool up = u * (1.f + __expf(-lg[k])) < 1.f;
         nb |= (up ? 1u : 0u) << k;
-        // log s(x) - log s(-x) = x: only the spins that change contribute
         const bool was_up = (cur >> k) & 1u;
         if (up != was_up) lratio += was_up ? lg[k] : -lg[k];
       }
@@ -519,7 +522,7 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       if (accept && nb != cur) *cr.bytep = (uint8_t)nb;
       if (!accept) dE = 0;
     }
-    wave_fence();  // logits read before the next tile's inputs overwrite them
+    wave_fence();
     add_cell_moves(St, moves, cr.r, valid, accept, dE, l);
   }
 }
@@ -530,8 +533,8 @@ hipError_t launch_cell_propose(const DevTables &t, const DevState &s, int32_t n_
   if (rows_total <= 0) return hipSuccess;
   const int64_t tiles = rows_total / 64;
   const int blocks = (int)std::min<int64_t>((tiles + kProposeWaves - 1) / kProposeWaves, 512);
-  hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(64 * kProposeWaves), 0, st, t, s, n_sys, rows_total, phase, w, wb, key,
-                     pass_index, moves);
+  hipLaunchKernelGGL(cell_propose_kernel, dim3(blocks), dim3(64 * kProposeWaves), 0, st, t, s, n_sys, rows_total,
+                     phase, w, wb, key, pass_index, moves);
   return hipGetLastError();
 }
 

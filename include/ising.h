@@ -118,8 +118,9 @@ int32_t ising_spin_layout(const ising_graph *g, int64_t *spin_word, int32_t *row
 /* Launch shapes.  Systems with the same template size and kernel variant
  * form a bucket, swept by one launch.  A walker's template columns are spread
  * over `tpw` threads (a power of two up to 64, which keeps a walker inside one
- * wavefront, or any count from 65 to 1024, walkers back to back; a thread
- * visits ceil(S/tpw) <= 8 columns per level) and a workgroup holds
+ * wavefront, or a count from 65 to 1024, walkers back to back; a thread visits
+ * ceil(S/tpw) <= 8 columns per level, at most 2 when tpw above 64 is not a
+ * multiple of 64) and a workgroup holds
  * `walkers_per_group` walkers.  Shapes change speed only: the
  * chain is the same for every shape.  bucket_info writes, in this order:
  *   S, systems, walkers, attempts per sweep, tpw, walkers per group, columns
@@ -194,8 +195,9 @@ int32_t ising_init_state(const ising_graph *g, ising_state *st, const uint32_t *
  * neighbours' local fields then current as in Figures 3 and 6); after each
  * sweep whose running count is a multiple of swap_every (> 0; 0 = never) one
  * swap round of every system (replica exchange, Section 1).  Long calls run as
- * several launches whose 32-bit per-launch counters cannot wrap; the chain is
- * the same.  e_series (device, nullable): [n_sweeps][slots] energy of the
+ * several launches whose 32-bit per-launch counters cannot wrap (and of at
+ * most n sweeps when the environment sets ISING_LAUNCH_SWEEPS_MAX=n); the
+ * chain is the same.  e_series (device, nullable): [n_sweeps][slots] energy of the
  * walker at each slot after each sweep and its swap round.  ISING_E_INVAL for
  * negative counts, ISING_E_STATE before ising_init_state.                    */
 int32_t ising_sweep(const ising_graph *g, ising_state *st, int32_t n_sweeps, int32_t swap_every,

@@ -24,7 +24,9 @@ __device__ __forceinline__ void philox4x32(uint32_t c[4], uint32_t k0, uint32_t 
       k1 += W1;
     }
     const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
-    const uint32_t x0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, x2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    // three-input xor (bit-operation table 0x96) in one instruction
+    const uint32_t x0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c[1], k0, 0x96);
+    const uint32_t x2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c[3], k1, 0x96);
     c[0] = x0;
     c[1] = (uint32_t)p1;
     c[2] = x2;

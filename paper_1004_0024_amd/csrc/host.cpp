@@ -399,8 +399,9 @@ Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles,
 }
 
 // Launch shape of a bucket: `tpw` threads per walker (a power of two up to 64,
-// or any count from 65 to 1024; each thread owns ceil(S/tpw) <= 8 columns) and
-// G walkers per workgroup.
+// a multiple of 64 up to 1024, or another count from 65 to 1024 when that
+// leaves at most two columns per thread; each thread owns ceil(S/tpw) <= 8
+// columns) and G walkers per workgroup.
 int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax, bool allow_ladder) {
   if (tpw < 1 || tpw > 1024 || (tpw <= 64 && (tpw & (tpw - 1)) != 0))
     return fail(ISING_E_RANGE, "tpw must be a power of two up to 64, or 65..1024");
@@ -408,6 +409,8 @@ int32_t shape_bucket(Bucket &b, int32_t tpw, int32_t G, int32_t Kmax, bool allow
   int32_t cpt = 1;
   while (cpt < need) cpt <<= 1;
   if (cpt > 8) return fail(ISING_E_RANGE, "tpw=%d leaves %d columns per thread (max 8)", tpw, need);
+  if (tpw > 64 && tpw % 64 != 0 && cpt > 2)
+    return fail(ISING_E_RANGE, "tpw=%d (not a multiple of 64) leaves %d columns per thread (max 2)", tpw, need);
   if (G < 1) return fail(ISING_E_RANGE, "G must be >= 1");
   G = std::min(G, Kmax);
   if ((int64_t)G * tpw > 1024) return fail(ISING_E_RANGE, "G*tpw exceeds 1024 threads");
@@ -643,7 +646,13 @@ int64_t bucket_sweep_limit(const GraphPlan &g, size_t b) {
 int64_t sweep_limit(const GraphPlan &g) {
   int64_t lim = INT32_MAX;
   for (size_t b = 0; b < g.buckets.size(); ++b) lim = std::min(lim, bucket_sweep_limit(g, b));
-  return lim;
+  return std::min(lim, launch_sweeps_cap());
+}
+
+int64_t launch_sweeps_cap() {
+  const char *v = getenv("ISING_LAUNCH_SWEEPS_MAX");
+  const long long n = v ? atoll(v) : 0;
+  return n >= 1 ? (int64_t)n : INT32_MAX;
 }
 
 // Layer-pair kernel: a walker flips at most N spins per sweep, and a lane (two
@@ -654,7 +663,7 @@ int64_t pairs_sweep_limit(const GraphPlan &g) {
     lim = std::min(lim, (int64_t)UINT32_MAX / ((int64_t)si.S * si.M));
     lim = std::min(lim, (int64_t)INT32_MAX / (2 * 63 * 2 * (int64_t)si.S));
   }
-  return std::max<int64_t>(lim, 1);
+  return std::max<int64_t>(std::min(lim, launch_sweeps_cap()), 1);
 }
 
 }  // namespace ising

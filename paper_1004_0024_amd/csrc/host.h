@@ -122,5 +122,9 @@ int64_t bucket_sweep_limit(const GraphPlan &g, size_t b);
 int64_t sweep_limit(const GraphPlan &g);
 // The same for the layer-pair kernel (flips of a walker, a lane's sum of d).
 int64_t pairs_sweep_limit(const GraphPlan &g);
+// A lower cap from the environment (ISING_LAUNCH_SWEEPS_MAX, when set to n >= 1):
+// calls then run as launches of at most n sweeps, which lets a test drive the
+// cut into segments without running 10^5 sweeps.
+int64_t launch_sweeps_cap();
 
 }  // namespace ising

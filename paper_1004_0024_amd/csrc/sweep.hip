@@ -71,7 +71,7 @@ __device__ __forceinline__ void level_sync() {
   }
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF, bool SHARED>
 __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, int32_t tile0, int32_t G,
                                                      int32_t TPW, int32_t PW, int32_t n_sweeps,
                                                      int32_t init_mode, LadderArgs la) {
@@ -284,7 +284,13 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   int dE = 0, nfl = 0;  // per lane: sum of d over flips (the cost changes by 2d), flips
   int dB = 0;           // per lane, two-field form: sum of d_t over flips (B changes by -2 d_t)
   int64_t n_rounds = 0;  // swap rounds run in this launch (ladder tiles)
-  uint32_t st_steps = 0, st_flip = 0, nfl_w = 0;  // per wavefront
+  uint32_t st_steps = 0, st_flip = 0, nfl_w = 0, nfl_0 = 0;  // per wavefront
+  // Flips are counted per lane when a wavefront holds several walkers of at
+  // most 64 threads, else per wavefront as popcounts of the flip ballot
+  // (scalar work only).  A SHARED wavefront (above 64 threads per walker, not a
+  // multiple of 64) holds lanes of at most two walkers: m0 marks those of its
+  // first lane's walker, nfl_0 counts their flips and nfl_w all flips.
+  const uint64_t m0 = SHARED ? __builtin_amdgcn_ballot_w64(gw == __builtin_amdgcn_readfirstlane(gw)) : ~0ull;
 
   gen_chunk(gslot, 0);
   gslot = advance(gslot);
@@ -308,7 +314,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     }
   } else {
     const int levels = M + F - 1;
-    const bool wave_walker = (TPW & 63) == 0;  // every wavefront's lanes belong to one walker
+    const bool wave_walker = !WS || TPW == 64;  // a wavefront's lanes belong to at most SHARED + 1 walkers
     for (int sw = 0; sw < n_sweeps; ++sw) {
       const int chunk0 = sw * M;
       for (int lv = 0; lv < levels; ++lv) {
@@ -369,8 +375,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             const uint64_t fl = __builtin_amdgcn_ballot_w64(le) & act;
             const bool flip = le && active;
             st_flip += fl != 0ull;
-            if (wave_walker) nfl_w += (uint32_t)__builtin_popcountll(fl);
-            else nfl += flip ? 1 : 0;
+            if (wave_walker) {
+              nfl_w += (uint32_t)__builtin_popcountll(fl);
+              if (SHARED) nfl_0 += (uint32_t)__builtin_popcountll(fl & m0);
+            } else {
+              nfl += flip ? 1 : 0;
+            }
             dE += flip ? d : 0;
             if (TF) dB += flip ? dt : 0;
             // wavefront-uniform: can any lane be on the first or last slice?
@@ -425,13 +435,17 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     atomicAdd(&acc[0], 2 * dE);
     if (TF && dB) atomicAdd(&acc[4], -2 * dB);
     if (nfl) atomicAdd(&acc[1], nfl);
-    // wavefront statistics (and, when a wavefront is one walker's, its flip
-    // count) go to the walker of the wavefront's first lane
-    if ((tid & 63) == 0) {
+    // wavefront statistics and the flips counted per wavefront go to the
+    // walker of the wavefront's first lane; in a SHARED wavefront the flips of
+    // the second walker's lanes (nfl_w - nfl_0) go to that walker's first lane
+    const int lane = tid & 63;
+    const uint32_t first = SHARED ? nfl_0 : nfl_w;
+    if (lane == 0) {
       atomicAdd(&acc[2], (int)st_steps);
       atomicAdd(&acc[3], (int)st_flip);
-      if (nfl_w) atomicAdd(&acc[1], (int)nfl_w);
+      if (first) atomicAdd(&acc[1], (int)first);
     }
+    if (SHARED && nfl_w != nfl_0 && lane == __builtin_ctzll(~m0)) atomicAdd(&acc[1], (int)(nfl_w - nfl_0));
   }
   __syncthreads();
   each_word(WW, [&](int w, int j) {
@@ -459,10 +473,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
   if (ladder) ladder_store(St, sy, tile.sys, tid, nthr, L, la.rounds0, n_rounds);
 }
 
-template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF>
+template <int NX, bool CELL, bool RING, int CPT, bool WS, bool LADDER, bool TF, bool SHARED = false>
 static hipError_t launch_variant(const DevTables &t, const DevState &s, const Bucket &b,
                                  int32_t n_sweeps, int32_t init_mode, hipStream_t st, LadderArgs la) {
-  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER, TF>;
+  auto kern = sweep_kernel<NX, CELL, RING, CPT, WS, LADDER, TF, SHARED>;
   // Allow the whole LDS once per instantiation and device.
   static std::atomic<uint64_t> lds_limit_set{0};
   if (b.lds > 64 * 1024) {
@@ -492,11 +506,19 @@ static hipError_t launch_cpt(const DevTables &t, const DevState &s, const Bucket
   } else {
     if (b.ladder) return hipErrorInvalidValue;  // the two-field form swaps in swap_kernel
   }
+  // above 64 threads per walker, a count that is not a multiple of 64 lets a
+  // wavefront hold two walkers (the host allows it with at most two columns)
+  const bool shared = !ws && (b.tpw & 63) != 0;
+  if (shared && b.cpt > 2) return hipErrorInvalidValue;
   switch (b.cpt) {
-    case 1: return ws ? launch_variant<NX, CELL, RING, 1, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 1, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
-    case 2: return ws ? launch_variant<NX, CELL, RING, 2, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
-                      : launch_variant<NX, CELL, RING, 2, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 1: return ws       ? launch_variant<NX, CELL, RING, 1, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                   : shared ? launch_variant<NX, CELL, RING, 1, false, false, TF, true>(t, s, b, n_sweeps, init_mode,
+                                                                                      st, la)
+                            : launch_variant<NX, CELL, RING, 1, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
+    case 2: return ws       ? launch_variant<NX, CELL, RING, 2, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
+                   : shared ? launch_variant<NX, CELL, RING, 2, false, false, TF, true>(t, s, b, n_sweeps, init_mode,
+                                                                                      st, la)
+                            : launch_variant<NX, CELL, RING, 2, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
     case 4: return ws ? launch_variant<NX, CELL, RING, 4, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)
                       : launch_variant<NX, CELL, RING, 4, false, false, TF>(t, s, b, n_sweeps, init_mode, st, la);
     case 8: return ws ? launch_variant<NX, CELL, RING, 8, true, false, TF>(t, s, b, n_sweeps, init_mode, st, la)

@@ -123,10 +123,12 @@ static void check_batch(const char *name, const std::vector<Sys> &systems) {
         Bucket b = orig;
         if (shape_bucket(b, tpw, G, Kmax, true) != ISING_OK) {
           CHECK(tpw > 1024 || (tpw <= 64 && (tpw & (tpw - 1))) || b.S > tpw * 8 || G * tpw > 1024 ||
+                (tpw > 64 && tpw % 64 && b.S > tpw * 2) ||
                 (size_t)G * b.walker_words * 4 > 160 * 1024);
           continue;
         }
         CHECK(b.cpt >= 1 && b.cpt <= 8 && (int64_t)b.tpw * b.cpt >= b.S);
+        CHECK(b.tpw <= 64 || b.tpw % 64 == 0 || b.cpt <= 2);
         CHECK(b.threads % 64 == 0 && b.threads <= 1024 && b.lds <= 160 * 1024);
         g.buckets[bi] = b;
         retile(g);

@@ -74,8 +74,8 @@ def test_buckets_spread_over_streams_keep_the_chain():
 ])
 def test_threads_per_walker_not_a_power_of_two(L, M, K, tpw, G):
     """Shapes with a thread count per walker above 64 that is not a power of two keep the
-    chain, the MT windows and every counter (flips are counted per lane when a wavefront
-    holds two walkers) bit for bit; swap rounds after single sweeps and a 7-sweep launch."""
+    chain, the MT windows and every counter (a wavefront that holds two walkers splits its flip
+    count between them by a lane mask) bit for bit; swap rounds after single sweeps and a 7-sweep launch."""
     wl = Workload(f"tpw {tpw} G {G}", [make_chimera_system(L, M, 800 + L, K)], 0, 1)
     g, st = make_state(wl)
     g.set_launch(0, tpw, G)

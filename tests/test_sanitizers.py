@@ -14,8 +14,8 @@ SAN = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
 
 
-def _run(exe):
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=ENV)
+def _run(exe, **env):
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=dict(ENV, **env))
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-6000:]
     return r.stdout
 
@@ -35,6 +35,13 @@ def test_host_planning_under_sanitizers(tmp_path):
     assert lim["C"] == min((2 ** 32 - 1) // 4096, (2 ** 31 - 1) // (2 * 63 * 32))
     assert all(v >= 1 for v in lim.values())
     assert out.count("reject ") == 10
+    # ISING_LAUNCH_SWEEPS_MAX lowers both limits (a value below 1 is ignored)
+    out = _run(exe, ISING_LAUNCH_SWEEPS_MAX="3")
+    pairs = {m.group(1): (int(m.group(2)), int(m.group(3)))
+             for m in re.finditer(r"^(\w+) systems .* sweep_limit (\d+) pairs_limit (\d+)", out, re.M)}
+    assert pairs.keys() == lim.keys() and all(v == (3, 3) for v in pairs.values())
+    out = _run(exe, ISING_LAUNCH_SWEEPS_MAX="0")
+    assert {m.group(1): int(m.group(2)) for m in re.finditer(r"^(\w+) systems .* sweep_limit (\d+)", out, re.M)} == lim
 
 
 def test_oracle_under_sanitizers(tmp_path):

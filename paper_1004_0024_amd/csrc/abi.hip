@@ -104,11 +104,14 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
       lo += h.S;
     }
   }
-  {
-    uint16_t *co = (uint16_t *)(host.data() + L.cells);
-    for (auto &h : hs) {
-      memcpy(co, h.cells.data(), sizeof(uint16_t) * h.cells.size());
-      co += h.cells.size();
+  {  // cell lists: index (m*L + y)*L + x -> (m << 16) | (y << 8) | x (L <= 255 for a grid)
+    uint32_t *co = (uint32_t *)(host.data() + L.cells);
+    for (size_t i = 0; i < hs.size(); ++i) {
+      const uint32_t gl = (uint32_t)std::max(g->sys[i].grid_L, 1);
+      for (uint16_t c : hs[i].cells) {
+        const uint32_t m = c / (gl * gl), y = (c / gl) % gl, x = c % gl;
+        *co++ = (m << 16) | (y << 8) | x;
+      }
     }
   }
   {
@@ -118,12 +121,15 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
       cr += h.cellrec.size();
     }
   }
-  {  // system of each 64-row tile of cell moves: the last system whose rows start at or before it
+  {  // each 64-row tile of cell moves: the last system whose rows start at or before it, and
+     // the walker of its first row (K for a tile of padding rows)
     int32_t *ts = (int32_t *)(host.data() + L.rtiles);
     int32_t sidx = 0;
     for (int64_t t = 0; t < g->cell_rows / 64; ++t) {
       while (sidx + 1 < n_sys && g->sys[sidx + 1].row0 <= t * 64) ++sidx;
-      ts[t] = sidx;
+      const SysInfo &si = g->sys[sidx];
+      ts[2 * t] = sidx;
+      ts[2 * t + 1] = si.rows > 0 ? (int32_t)std::min<int64_t>((t * 64 - si.row0) / si.rows, si.K) : si.K;
     }
   }
   memcpy(host.data() + L.tiles, g->tiles.data(), sizeof(Tile) * g->tiles.size());
@@ -144,8 +150,8 @@ extern "C" int32_t ising_load_graph(const ising_system_desc *sys, int32_t n_sys,
   g->dev.walker_sys = (const int32_t *)(base + L.wsys);
   g->dev.fifo = (const uint32_t *)(base + L.fifo);
   g->dev.lanes = (const uint16_t *)(base + L.lanes);
-  g->dev.cells = (const uint16_t *)(base + L.cells);
-  g->dev.tile_sys = (const int32_t *)(base + L.rtiles);
+  g->dev.cells = (const uint32_t *)(base + L.cells);
+  g->dev.cell_tiles = (const int2 *)(base + L.rtiles);
   g->dev.cellrec = (const uint32_t *)(base + L.cellrec);
   g->dev.qthr = (const uint32_t *)(base + L.qthr);
   g->dev.qa = (const double *)(base + L.qa);

@@ -152,36 +152,41 @@ struct CellRow {
 
 struct TileSys {
   int M, L, LL, RS, WW, ring, K, walker0, slot0, cb0, rows, cl0, p0, count, fast;
-  long long spin_word0, row0;
+  int w0, j0;  // walker and cell-list position of the tile's first row
+  long long spin_word0;
 };
 
-__device__ __forceinline__ long long uniform64(long long v) {
-  return ((long long)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
-         (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+// Tables the kernels only read, through the scalar cache: with a uniform
+// address the loads are scalar and land in scalar registers.
+template <typename V>
+__device__ __forceinline__ V load_uniform(const V *p) {
+  return *(const __attribute__((address_space(4))) V *)p;
 }
 
 __device__ __forceinline__ TileSys tile_system(const DevTables &T, int64_t tile, int phase) {
-  const int sidx = __builtin_amdgcn_readfirstlane(T.tile_sys[tile]);
+  const long long td = load_uniform((const long long *)(T.cell_tiles + tile));  // {system, w0}
+  const int sidx = (int)(uint32_t)td, w0 = (int)(td >> 32);
   const SysInfo *sy = T.sys + sidx;
   TileSys u;
-  u.M = __builtin_amdgcn_readfirstlane(sy->M);
-  u.L = __builtin_amdgcn_readfirstlane(sy->grid_L);
+  u.M = load_uniform(&sy->M);
+  u.L = load_uniform(&sy->grid_L);
   u.LL = u.L * u.L;
-  u.RS = __builtin_amdgcn_readfirstlane(sy->RS);
-  u.WW = __builtin_amdgcn_readfirstlane(sy->WW);
-  u.ring = __builtin_amdgcn_readfirstlane(sy->ring);
-  u.K = __builtin_amdgcn_readfirstlane(sy->K);
-  u.walker0 = __builtin_amdgcn_readfirstlane(sy->walker0);
-  u.slot0 = __builtin_amdgcn_readfirstlane(sy->slot0);
-  u.cb0 = __builtin_amdgcn_readfirstlane(sy->cb0);
-  u.rows = __builtin_amdgcn_readfirstlane(sy->rows);
-  u.cl0 = __builtin_amdgcn_readfirstlane(sy->cl0);
-  u.fast = __builtin_amdgcn_readfirstlane(sy->cell_fast);
-  const int np = __builtin_amdgcn_readfirstlane(sy->n_phases);
-  u.p0 = phase < np ? __builtin_amdgcn_readfirstlane(sy->pc[phase]) : 0;
-  u.count = phase < np ? __builtin_amdgcn_readfirstlane(sy->pc[phase + 1]) - u.p0 : 0;
-  u.spin_word0 = uniform64(sy->spin_word0);
-  u.row0 = uniform64(sy->row0);
+  u.RS = load_uniform(&sy->RS);
+  u.WW = load_uniform(&sy->WW);
+  u.ring = load_uniform(&sy->ring);
+  u.K = load_uniform(&sy->K);
+  u.walker0 = load_uniform(&sy->walker0);
+  u.slot0 = load_uniform(&sy->slot0);
+  u.cb0 = load_uniform(&sy->cb0);
+  u.rows = load_uniform(&sy->rows);
+  u.cl0 = load_uniform(&sy->cl0);
+  u.fast = load_uniform(&sy->cell_fast);
+  const int np = load_uniform(&sy->n_phases);
+  u.p0 = phase < np ? load_uniform(&sy->pc[phase]) : 0;
+  u.count = phase < np ? load_uniform(&sy->pc[phase + 1]) - u.p0 : 0;
+  u.spin_word0 = load_uniform(&sy->spin_word0);
+  u.w0 = w0;
+  u.j0 = (int)(tile * 64 - load_uniform(&sy->row0)) - w0 * u.rows;
   return u;
 }
 
@@ -197,18 +202,27 @@ __device__ __forceinline__ TileSys tile_system(const DevTables &T, int64_t tile,
 // four bits are (word >> k) & 0x01010101 and one byte dot product with the
 // couplings by direction sums them; otherwise each of the record's entries
 // names the neighbour's bit.
-__device__ __forceinline__ void load_row(const DevTables &T, const DevState &St, const TileSys &u, int64_t tile,
-                                         int lane, CellRow &c) {
-  const uint32_t local = (uint32_t)(tile * 64 + lane - u.row0);
-  const int wk = (int)(local / (uint32_t)u.rows), j = (int)(local - (uint32_t)wk * (uint32_t)u.rows);
+__device__ __forceinline__ void load_row(const DevTables &T, const DevState &St, const TileSys &u, int lane,
+                                         CellRow &c) {
+  // rows are walker-major, `rows` per walker: the tile's first row is (w0, j0)
+  int wk = u.w0, j = u.j0 + lane;
+  if (u.rows >= 64) {  // at most one walker boundary in the tile
+    const bool next = j >= u.rows;
+    wk += next ? 1 : 0;
+    j -= next ? u.rows : 0;
+  } else {
+    const int q = j / u.rows;
+    wk += q;
+    j -= q * u.rows;
+  }
   c.valid = wk < u.K && j < u.count;
   const int wkc = c.valid ? wk : 0, jc = c.valid ? j : 0;
   c.r = c.valid ? u.walker0 + wk : -1;
-  const int ci = (int)T.cells[u.cl0 + u.p0 + jc];
+  const uint32_t pc = T.cells[u.cl0 + u.p0 + jc];
   const int tof = St.temp_of[u.walker0 + wkc];
-  c.ci = ci;
-  const int m = ci / u.LL, cc = ci - m * u.LL;
-  const int y = cc / u.L, x = cc - y * u.L;
+  const int m = (int)(pc >> 16), y = (int)((pc >> 8) & 0xffu), x = (int)(pc & 0xffu);
+  const int cc = y * u.L + x;
+  c.ci = m * u.LL + cc;
   const uint32_t *sp = St.spins + u.spin_word0 + (size_t)wkc * u.WW;
   const uint32_t *row = sp + m * u.RS;
   const int mp = m == 0 ? u.M - 1 : m - 1, mn = m == u.M - 1 ? 0 : m + 1;
@@ -412,7 +426,7 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
   const TileRange tr = wave_tiles(rows_total / 64, kProposeWaves);
   for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     CellRow cr;
-    load_row(T, St, tile_system(T, tile, phase), tile, l, cr);
+    load_row(T, St, tile_system(T, tile, phase), l, cr);
     const bool valid = cr.valid;
     const int *b = cr.b;
     const float beta = cr.beta;
@@ -423,6 +437,11 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       xr[1] = u32x4{(uint32_t)f2bf(beta), 0u, 0u, 0u};
     }
     wave_fence();
+    // A wavefront in the network raises its priority, so its matrix-core work
+    // is issued first and the other wavefronts' vector work fills around it
+    // (3-4% faster than without; forcing two wavefront groups into opposite
+    // phases with barriers was slower).
+    __builtin_amdgcn_s_setprio(1);
     const f32x4 bias3 = *(const f32x4 *)(s.b3 + 4 * (g & 3));
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -477,6 +496,7 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
           for (int j = 0; j < 4; ++j) Lg[((2 * half + tt) * 16 + n16) * 8 + 4 * g + j] = acc3[tt][j];
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     wave_fence();
 
     int dE = 0;
@@ -555,7 +575,7 @@ __global__ void __launch_bounds__(256) cell_heatbath_kernel(DevTables T, DevStat
   const TileRange tr = wave_tiles(rows_total / 64, 4);
   for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     CellRow cr;
-    load_row(T, St, tile_system(T, tile, phase), tile, l, cr);
+    load_row(T, St, tile_system(T, tile, phase), l, cr);
     int dE = 0;
     bool changed = false;
     if (cr.valid) {

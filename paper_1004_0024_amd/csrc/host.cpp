@@ -383,9 +383,9 @@ Layout layout_for(int64_t n_sys, int64_t n_tmpl, int64_t slots, int64_t n_tiles,
   L.wsys = o;
   o = align256(o + sizeof(int32_t) * R);
   L.cells = o;
-  o = align256(o + sizeof(uint16_t) * std::max<int64_t>(n_cells, 1));
+  o = align256(o + sizeof(uint32_t) * std::max<int64_t>(n_cells, 1));
   L.rtiles = o;
-  o = align256(o + sizeof(int32_t) * std::max<int64_t>(cell_rows / 64, 1));
+  o = align256(o + 2 * sizeof(int32_t) * std::max<int64_t>(cell_rows / 64, 1));
   L.cellrec = o;
   o = align256(o + sizeof(uint32_t) * std::max<int64_t>(n_cellrec, 1));
   L.qthr = o;  // two-field threshold rows

@@ -138,8 +138,8 @@ struct DevTables {
   const int32_t *walker_sys;  // [R] system of each walker
   const uint32_t *fifo;       // per template spin: (queue base << 8) | log2(queue depth)
   const uint16_t *lanes;      // per template: sweep lane position -> template spin
-  const uint16_t *cells;      // per system, per phase: cell indices (m*L + y)*L + x
-  const int32_t *tile_sys;    // per 64-row tile of cell moves: its system
+  const uint32_t *cells;      // per system, per phase: cells as (m << 16) | (y << 8) | x
+  const int2 *cell_tiles;     // per 64-row tile of cell moves: its system, the walker of its first row
   const uint32_t *cellrec;    // cell records of the grid templates (see kCellRecWords)
   // two-field form: per-slot weights (a, c) and threshold rows of qrow words
   const uint32_t *qthr;       // [slots][qrow]

@@ -30,23 +30,28 @@ LANE_OPS_PER_ATTEMPT = 60
 LANE_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 FLOPS_PER_CELL = 2 * (17 * 128 + 128 * 128 + 128 * 8)  # one network evaluation: 39,168
 METRIC = "spin-flip attempts/s + effective samples/s (plain vs learned proposal), 1 GPU"
-# Measured HBM traffic and VALU issue of the sweep kernel come from the committed rocprofv3 summary
-# of the workload (a "measured:" JSON line in profiles/sweep_kernel_<config>_counters.md), and are
-# reported only while the kernel's sources hash to the value recorded there.
+# Measured HBM traffic and issue figures of a kernel come from the committed rocprofv3 summary of
+# its workload (a "measured:" JSON line in the profile), and are reported only while the kernel's
+# sources hash to the value recorded there.
 SWEEP_SOURCES = ["sweep.hip", "internal.h", "mt19937.h", "swap_round.h"]
+CELL_SOURCES = ["cells.hip", "internal.h", "mlp.h"]
 
 
-def sweep_sources_hash():
+def sources_hash(names):
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_1004_0024_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_counters(config):
+def sweep_sources_hash():
+    return sources_hash(SWEEP_SOURCES)
+
+
+def measured_counters(config, profile=None, sources=SWEEP_SOURCES):
     """(figures, why): the profile's measured line when its source hash matches, else None."""
-    path = os.path.join("profiles", f"sweep_kernel_{config}_counters.md")
+    path = os.path.join("profiles", profile or f"sweep_kernel_{config}_counters.md")
     try:
         text = open(os.path.join(ROOT, path)).read()
     except OSError:
@@ -55,9 +60,9 @@ def measured_counters(config):
     if not m:
         return None, f"{path} has no measured line"
     fig = json.loads(m.group(1))
-    now = sweep_sources_hash()
+    now = sources_hash(sources)
     if fig.get("sources_sha256") != now:
-        return None, f"stale: {path} was taken with sweep sources {fig.get('sources_sha256')}, now {now}"
+        return None, f"stale: {path} was taken with sources {fig.get('sources_sha256')}, now {now}"
     fig["source"] = path
     return fig, None
 
@@ -384,6 +389,17 @@ def learned_leg(ess_steps, train_rows=1 << 20, burn_in=20000):
             "heatbath_over_plain": per_s["heatbath"] / per_s["plain"],
             "summed_over_matched_slots": {"learned_over_plain": tot["learned"] / tot["plain"],
                                           "heatbath_over_plain": tot["heatbath"] / tot["plain"]}})
+    cell_roofline = {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
+                     "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,
+                     "cells_per_launch": cells_per_pass / (launches / passes), "traffic": None,
+                     "traffic_unit": "HBM bytes per launch"}
+    fig, why = measured_counters("E", "cell_propose_kernel_E.md", CELL_SOURCES)
+    if fig is not None:
+        cell_roofline["traffic"] = fig["hbm_bytes_per_launch"]
+        cell_roofline["measured"] = {k: fig.get(k) for k in ("source", "sources_sha256", "mfma_busy", "valu_busy")}
+    else:
+        cell_roofline["traffic_note"] = why
     return {
         "workload": wl.name, "steps": ess_steps, "burn_in_sweeps": burn_in,
         "matched_accuracy": matched,
@@ -402,10 +418,7 @@ def learned_leg(ess_steps, train_rows=1 << 20, burn_in=20000):
         # standard errors (per system and slot)
         "means_vs_plain": {k: v for k, v in comp.items() if k != "plain_next"},
         "plain_vs_its_next_stretch": comp["plain_next"],
-        "roofline": {"bound": "mfma", "kernel": "cell_propose_kernel", "kernel_avg_ms": launch_ms,
-                     "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_cell": FLOPS_PER_CELL,
-                     "cells_per_launch": cells_per_pass / (launches / passes), "traffic": None},
+        "roofline": cell_roofline,
     }
 
 

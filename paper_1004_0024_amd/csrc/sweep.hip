@@ -25,7 +25,8 @@
 // one wavefront and a level ends with a wavefront fence instead of a workgroup
 // barrier; above 64 the walkers of a workgroup lie back to back, so with TPW
 // not a multiple of 64 a wavefront can hold the end of one walker and the
-// start of the next.
+// start of the next (the SHARED instantiations, at most two columns per
+// thread).
 //
 // Data in LDS for the whole launch, per walker:
 //  - spins, one bit each, slice rows of RS words (RS odd when > 1, so rows of

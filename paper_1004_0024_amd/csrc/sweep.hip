@@ -318,6 +318,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
     const bool wave_walker = !WS || TPW == 64;  // a wavefront's lanes belong to at most SHARED + 1 walkers
     for (int sw = 0; sw < n_sweeps; ++sw) {
       const int chunk0 = sw * M;
+      const int gen_levels = sw + 1 < n_sweeps ? M : M - 1;  // levels that generate a chunk
       for (int lv = 0; lv < levels; ++lv) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -375,9 +376,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             const bool le = u <= thv;
             const uint64_t fl = __builtin_amdgcn_ballot_w64(le) & act;
             const bool flip = le && active;
-            st_flip += fl != 0ull;
+            const uint32_t nfl_step = (uint32_t)__builtin_popcountll(fl);
+            st_flip += nfl_step != 0u ? 1u : 0u;
             if (wave_walker) {
-              nfl_w += (uint32_t)__builtin_popcountll(fl);
+              nfl_w += nfl_step;
               if (SHARED) nfl_0 += (uint32_t)__builtin_popcountll(fl & m0);
             } else {
               nfl += flip ? 1 : 0;
@@ -397,11 +399,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             }
           }
         }
-        if (lv + 1 < M) {
+        // the next chunk: slice lv + 1 of this sweep, or slice 0 of the next
+        if (lv < gen_levels) {
           gen_chunk(gslot, chunk0 + lv + 1);
-          gslot = advance(gslot);
-        } else if (lv == M - 1 && sw + 1 < n_sweeps) {
-          gen_chunk(gslot, chunk0 + M);
           gslot = advance(gslot);
         }
         level_sync<WS>();

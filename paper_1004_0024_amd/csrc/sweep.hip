@@ -392,10 +392,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(DevTables T, DevState St, i
             if (flip) {
               const uint32_t bit = 1u << qb[c];
               atomicXor(own_p, bit);
-              if (edge) {  // keep the halo copy of the first / last slice
-                if (mm == 0) atomicXor(own_p + WW, bit);
-                if (mm == M - 1) atomicXor(own_p - WW, bit);
-              }
+              // keep the halo copy of the first / last slice (M >= 3 on a ring)
+              if (edge && (mm == 0 || mm == M - 1)) atomicXor(own_p + (mm == 0 ? WW : -WW), bit);
             }
           }
         }

@@ -238,18 +238,22 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
                           (cell_byte(wr, cr) << 24);
   const uint32_t bp = has_p ? cell_byte(wp, cc) : 0u, bn = has_n ? cell_byte(wn, cc) : 0u;
   if (u.fast) {
-    const uint4 d0 = rec[6], d1 = rec[7];
+    // f_k = h''_k + sum_dir 2J bit + jtau_k U_k, with h''_k = h_k - sum_dir J - 2 jtau_k
+    // from the record and U_k = 2 (bit k of the slice before, if any) + 2 (bit k
+    // of the slice after, if any) + the number of missing tau neighbours, built
+    // for all eight spins as bytes (0..4, no carries)
+    const uint4 d0 = rec[6], d1 = rec[7], hx = rec[8];
     const uint32_t dir[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    const uint32_t pm = has_p ? bp : 0u, nm = has_n ? bn : 0u;
+    const uint32_t miss = (has_p ? 0u : 0x01010101u) + (has_n ? 0u : 0x01010101u);
+    const uint32_t U[2] = {2u * (spread4(pm & 15u) + spread4(nm & 15u)) + miss,
+                           2u * (spread4(pm >> 4) + spread4(nm >> 4)) + miss};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int h = (int)(int8_t)((((k < 4) ? hq.x : hq.y) >> (8 * (k & 3))) & 0xffu);
+      const int h2 = (int)(int8_t)((((k < 4) ? hx.x : hx.y) >> (8 * (k & 3))) & 0xffu);
       const int jtau = (int)(int8_t)((((k < 4) ? hq.z : hq.w) >> (8 * (k & 3))) & 0xffu);
-      // h + sum_dir J (2 bit - 1) = h + sum 2J bit - sum 2J / 2
-      int f = h + __builtin_amdgcn_sdot4((int)((nbytes >> k) & 0x01010101u), (int)dir[k], 0, false) -
-              (__builtin_amdgcn_sdot4(0x01010101, (int)dir[k], 0, false) >> 1);
-      if (has_p) f += jtau * (2 * (int)((bp >> k) & 1u) - 1);
-      if (has_n) f += jtau * (2 * (int)((bn >> k) & 1u) - 1);
-      c.b[k] = c.valid ? f : 0;
+      const int uk = (int)((U[k >> 2] >> (8 * (k & 3))) & 0xffu);
+      c.b[k] = __builtin_amdgcn_sdot4((int)((nbytes >> k) & 0x01010101u), (int)dir[k], h2, false) + jtau * uk;
     }
   } else {
     const uint4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
@@ -288,7 +292,11 @@ struct TileRange {
 __device__ __forceinline__ TileRange wave_tiles(int64_t tiles, int waves_per_group) {
   const int64_t nwaves = (int64_t)gridDim.x * waves_per_group;
   const int64_t per = (tiles + nwaves - 1) / nwaves;
-  const int64_t w = (int64_t)blockIdx.x * waves_per_group + (threadIdx.x >> 6);
+  // the wavefront's index, read from lane 0: the compiler then knows the range is
+  // uniform, keeps the tile loop in scalar registers and loads the tile's tables
+  // through the scalar cache
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t w = (int64_t)blockIdx.x * waves_per_group + wave;
   const int64_t b = w * per;
   return TileRange{b < tiles ? b : tiles, b + per < tiles ? b + per : tiles};
 }

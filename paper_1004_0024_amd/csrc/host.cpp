@@ -334,6 +334,10 @@ int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &out) {
           rec[16 + (k >> 2)] |= (uint32_t)(uint8_t)t.h << (8 * (k & 3));
           rec[18 + (k >> 2)] |= (uint32_t)(uint8_t)t.Jtau << (8 * (k & 3));
           if (k < 4) rec[20 + k] = (uint32_t)t.jpack;
+          int32_t hc = t.h - 2 * t.Jtau;  // the field's constant part with s = 2 bit - 1
+          for (int32_t j = 4; j < t.deg; ++j) hc -= t.J[j];
+          if (hc < -128 || hc > 127) out.cell_fast = 0;
+          rec[32 + (k >> 2)] |= (uint32_t)(uint8_t)(int8_t)hc << (8 * (k & 3));
         }
       }
     }

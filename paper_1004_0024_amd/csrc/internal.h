@@ -68,8 +68,11 @@ static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
 //   [20 + k]      2J of spin k (< 4) to the spins 4 + i of the cell, byte i;
 //   [24 + k]      when the system's cell_fast is set: 2J of spin k to spin k of
 //                 the cell above, below, left and right, bytes 0..3 (0 where
-//                 there is none), matching the byte order of the word above.
-constexpr int kCellRecWords = 32;
+//                 there is none), matching the byte order of the word above;
+//   [32], [33]    when cell_fast is set: h_k - sum_dir J - 2 J_tau as int8,
+//                 k = 0..3 and 4..7 (the constant part of the boundary field when
+//                 bits stand for spins: s = 2 bit - 1); [34], [35] unused.
+constexpr int kCellRecWords = 40;
 
 // One workgroup of the sweep: `nw` walkers of system `sys` starting at `w0`.
 struct Tile {

@@ -57,30 +57,39 @@ def train(net, x, y, batch=4096, epochs=2, lr=1e-3):
     return torch.stack([l.reshape(()) for l in losses]).cpu().numpy()
 
 
-def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False, cell_every=1):
+def run(state, steps, net=None, key=0, pass0=0, swap_every=1, heatbath=False, cell_every=1, time_cells=False):
     """`steps` steps of the chain: a sweep and its swap round, then, with a network, one
     pass of learned cell moves, or with `heatbath`, one pass of exact heat-bath cell
     moves, after every `cell_every`-th step.  Returns slot energies [steps, slots] (host),
-    GPU ms and the fraction of cells accepted (learned) or changed (heat-bath)."""
+    GPU ms and the fraction of cells accepted (learned) or changed (heat-bath).  With
+    `time_cells`, HIP events around every pass also give its GPU time ("cell_pass_ms")."""
     import torch
     g = state.graph
     e = torch.zeros((steps, g.slots), dtype=torch.int32, device=g.tables.device)
     cells = net is not None or heatbath
     moves = torch.zeros((g.R, 2), dtype=torch.int64, device=g.tables.device) if cells else None
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = []
     torch.cuda.synchronize()
     t0.record()
     for t in range(steps):
         state.sweep(1, swap_every)
-        if (t + 1) % cell_every == 0:
+        if cells and (t + 1) % cell_every == 0:
+            if time_cells:
+                evs.append((torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)))
+                evs[-1][0].record()
             if net is not None:
                 state.propose_cells(net, key, pass0 + t, moves)
-            elif heatbath:
+            else:
                 state.heatbath_cells(key, pass0 + t, moves)
+            if time_cells:
+                evs[-1][1].record()
         state.record(e[t])
     t1.record()
     torch.cuda.synchronize()
     out = {"e": e.cpu().numpy(), "ms": t0.elapsed_time(t1)}
+    if time_cells:
+        out["cell_pass_ms"] = [a.elapsed_time(b) for a, b in evs]
     if moves is not None:
         mv = moves.cpu().numpy()
         out["acceptance"] = float(mv[:, 1].sum()) / max(1.0, float(mv[:, 0].sum()))

@@ -115,25 +115,29 @@ __device__ __forceinline__ int cell_energy(uint32_t byte, const int b[8], const 
   return e;
 }
 
-// E_c(s') - E_c(s) with packed byte products: for a cell byte s (bit k = spin k
-// is +1), sum_k b_k s_k = 2 sum_k b_k bit_k - sum_k b_k, and for a left spin k,
-// 2 sum_r J_kr s_r = 2 sum_r 2J_kr bit_r - sum_r 2J_kr, each sum one 4-way byte
+// E_c(s') - E_c(s) with packed byte products, for cell bytes s' = nb and s = cur
+// (bit k = spin k is +1).  With s = 2 bit - 1, sum_k b_k s_k = 2 sum_k b_k bit_k
+// - sum_k b_k, whose constant cancels in the difference, and for a left spin k,
+// T_k = sum_r J_kr s_r = sum_r 2J_kr bit_r - jsum_k; each sum is one 4-way byte
 // dot product.  blo / bhi hold b_0..b_3 / b_4..b_7 as signed bytes (|b| <= 63),
-// jpack[k] the 2J of left spin k to right spins 0..3, jsum2[k] their sum.
+// jpack[k] the 2J of left spin k to right spins 0..3, njs[k] = -jsum_k.
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) { return __umul24(nib, 0x00204081u) & 0x01010101u; }
 
-__device__ __forceinline__ int cell_energy_packed(uint32_t byte, uint32_t blo, uint32_t bhi, int bsum,
-                                                  const int32_t jpack[4], const int jsum2[4]) {
-  const uint32_t sl = spread4(byte & 15u), sr = spread4(byte >> 4);
-  const int bs = 2 * (__builtin_amdgcn_sdot4((int)sl, (int)blo, 0, false) +
-                      __builtin_amdgcn_sdot4((int)sr, (int)bhi, 0, false)) - bsum;  // sum_k b_k s_k
-  int js2 = 0;  // 2 sum_{k, r} J_kr s_k s_r
+__device__ __forceinline__ int cell_delta_e(uint32_t nb, uint32_t cur, uint32_t blo, uint32_t bhi,
+                                            const int32_t jpack[4], const int njs[4]) {
+  const uint32_t rn = spread4(nb >> 4), rc = spread4(cur >> 4);
+  const int bn = __builtin_amdgcn_sdot4((int)spread4(nb & 15u), (int)blo,
+                                        __builtin_amdgcn_sdot4((int)rn, (int)bhi, 0, false), false);
+  const int bc = __builtin_amdgcn_sdot4((int)spread4(cur & 15u), (int)blo,
+                                        __builtin_amdgcn_sdot4((int)rc, (int)bhi, 0, false), false);
+  int js = 0;  // sum_k s'_k T'_k - sum_k s_k T_k
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int t = 2 * __builtin_amdgcn_sdot4((int)sr, jpack[k], 0, false) - jsum2[k];
-    js2 += ((byte >> k) & 1u) ? t : -t;
+    const int tn = __builtin_amdgcn_sdot4((int)rn, jpack[k], njs[k], false);
+    const int tc = __builtin_amdgcn_sdot4((int)rc, jpack[k], njs[k], false);
+    js += (((nb >> k) & 1u) ? tn : -tn) - (((cur >> k) & 1u) ? tc : -tc);
   }
-  return -bs - js2 / 2;
+  return -2 * (bn - bc) - js;
 }
 
 // ---- rows of a colour class ---------------------------------------------------
@@ -145,6 +149,7 @@ struct CellRow {
   int r, ci;           // global walker, cell index (m*L + y)*L + x
   int b[8];            // boundary fields
   int32_t jpack[4];    // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
+  int njs[4];          // minus the sum over i of J between spin k < 4 and spin 4 + i
   float beta;
   uint8_t *bytep;      // the cell's byte in the walker's spin words
   uint32_t cur;        // its current value (bit k = spin k is +1)
@@ -237,12 +242,13 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
   const uint32_t nbytes = cell_byte(wu, cu) | (cell_byte(wdn, cd) << 8) | (cell_byte(wl, cl) << 16) |
                           (cell_byte(wr, cr) << 24);
   const uint32_t bp = has_p ? cell_byte(wp, cc) : 0u, bn = has_n ? cell_byte(wn, cc) : 0u;
+  const uint4 hx = rec[8];
   if (u.fast) {
     // f_k = h''_k + sum_dir 2J bit + jtau_k U_k, with h''_k = h_k - sum_dir J - 2 jtau_k
     // from the record and U_k = 2 (bit k of the slice before, if any) + 2 (bit k
     // of the slice after, if any) + the number of missing tau neighbours, built
     // for all eight spins as bytes (0..4, no carries)
-    const uint4 d0 = rec[6], d1 = rec[7], hx = rec[8];
+    const uint4 d0 = rec[6], d1 = rec[7];
     const uint32_t dir[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
     const uint32_t pm = has_p ? bp : 0u, nm = has_n ? bn : 0u;
     const uint32_t miss = (has_p ? 0u : 0x01010101u) + (has_n ? 0u : 0x01010101u);
@@ -279,6 +285,10 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
   c.jpack[1] = (int32_t)jq.y;
   c.jpack[2] = (int32_t)jq.z;
   c.jpack[3] = (int32_t)jq.w;
+  c.njs[0] = (int)(int16_t)(hx.z & 0xffffu);
+  c.njs[1] = (int)(int32_t)hx.z >> 16;
+  c.njs[2] = (int)(int16_t)(hx.w & 0xffffu);
+  c.njs[3] = (int)(int32_t)hx.w >> 16;
   c.bytep = (uint8_t *)(St.spins + u.spin_word0 + (size_t)wkc * u.WW + m * u.RS + (cc >> 2)) + (cc & 3);
   c.cur = cell_byte(wo, cc);
   c.beta = c.valid ? (float)T.beta[u.slot0 + tof] : 0.f;
@@ -527,24 +537,20 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       float lratio = 0.f;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const float u = (float)wd[k] * 0x1p-32f;
-        const bool up = u * (1.f + __expf(-lg[k])) < 1.f;
+        // u (1 + e^-l) < 1 with u = word 2^-32, scaled by 2^32 (exact in FP32)
+        const bool up = (float)wd[k] * (1.f + __expf(-lg[k])) < 0x1p32f;
         nb |= (up ? 1u : 0u) << k;
         const bool was_up = (cur >> k) & 1u;
         if (up != was_up) lratio += was_up ? lg[k] : -lg[k];
       }
       {
         uint32_t blo = 0, bhi = 0;
-        int bsum = 0, jsum2[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           blo |= (uint32_t)(b[k] & 0xff) << (8 * k);
           bhi |= (uint32_t)(b[4 + k] & 0xff) << (8 * k);
-          bsum += b[k] + b[4 + k];
-          jsum2[k] = __builtin_amdgcn_sdot4(0x01010101, cr.jpack[k], 0, false);
         }
-        dE = cell_energy_packed(nb, blo, bhi, bsum, cr.jpack, jsum2) -
-             cell_energy_packed(cur, blo, bhi, bsum, cr.jpack, jsum2);
+        dE = cell_delta_e(nb, cur, blo, bhi, cr.jpack, cr.njs);
       }
       const float la = -beta * (float)dE + lratio;
       const float ua = (float)wd[8] * 0x1p-32f;

@@ -338,6 +338,11 @@ int32_t build_system(const ising_system_desc &d, int32_t idx, SysHost &out) {
           for (int32_t j = 4; j < t.deg; ++j) hc -= t.J[j];
           if (hc < -128 || hc > 127) out.cell_fast = 0;
           rec[32 + (k >> 2)] |= (uint32_t)(uint8_t)(int8_t)hc << (8 * (k & 3));
+          if (k < 4) {  // minus the sum of J from spin k to spins 4..7 of the cell, int16
+            int32_t js = 0;
+            for (int32_t i = 0; i < 4; ++i) js += (int32_t)(int8_t)((uint32_t)t.jpack >> (8 * i)) / 2;
+            rec[34 + (k >> 1)] |= (uint32_t)(uint16_t)(int16_t)(-js) << (16 * (k & 1));
+          }
         }
       }
     }

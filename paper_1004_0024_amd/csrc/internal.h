@@ -71,7 +71,9 @@ static_assert(sizeof(TmplSpin) == 32, "template record is 32 bytes");
 //                 there is none), matching the byte order of the word above;
 //   [32], [33]    when cell_fast is set: h_k - sum_dir J - 2 J_tau as int8,
 //                 k = 0..3 and 4..7 (the constant part of the boundary field when
-//                 bits stand for spins: s = 2 bit - 1); [34], [35] unused.
+//                 bits stand for spins: s = 2 bit - 1);
+//   [34], [35]    minus the sum over i of J between spin k < 4 and spin 4 + i,
+//                 int16, k = 0, 1 and 2, 3.
 constexpr int kCellRecWords = 40;
 
 // One workgroup of the sweep: `nw` walkers of system `sys` starting at `w0`.

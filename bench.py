@@ -122,12 +122,16 @@ def progress(*a):
 def tuned_graph(wl, reps=3):
     """The workload's graph with the launch shapes the autotuner picks (timed on a
     scratch state), as every timed leg here uses it; the parity tests call this
-    too, so they run the shapes that are timed."""
+    too, so they run the shapes that are timed.  With several buckets, which run
+    side by side, the shapes are then refined by the time of the whole sweep
+    (tune.refine_shapes_side_by_side; its steps in g.side_by_side)."""
     import paper_1004_0024_amd as pa
+    from paper_1004_0024_amd import tune
 
     g = pa.Graph(wl.systems)
     scratch = pa.State(g).init(wl.walker_seeds, wl.swap_seeds)
     trials = g.autotune(scratch, reps=reps)
+    g.side_by_side = tune.refine_shapes_side_by_side(scratch)
     del scratch
     return g, trials
 
@@ -174,6 +178,7 @@ def batch_leg(name, n_sweeps, reps=3):
             "buckets": len(g.buckets()), "ms_per_sweep": ms / n_sweeps,
             "launch_shapes": [{k: b[k] for k in ("S", "tpw", "G", "cpt", "threads", "lds", "stream", "work")}
                               for b in g.buckets()],
+            "side_by_side_refinement": g.side_by_side,
             "value": rate, "unit": "spin-flip attempts/s",
             # the whole replay (sweep kernels, swap rounds, side-stream joins) against the 12 B model
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -458,6 +463,8 @@ def main():
                     help="chain steps per ESS estimate in the learned-proposal leg")
     ap.add_argument("--burn-in", type=int, default=20000,
                     help="plain sweeps before the learned-proposal leg collects and compares")
+    ap.add_argument("--bucket-shapes", action="store_true",
+                    help="also time the uneven batch's whole sweep with each bucket in its other launch shapes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the whole path runs on a single MI355X "
@@ -578,6 +585,13 @@ def main():
         for name, n, reps in (("A", 1000, 3), ("C", 200, 3), ("D", 1000, 2)):
             out["other_shapes"].append(batch_leg(name, n, reps))
             progress("workload", name, f"{out['other_shapes'][-1]['value']:.4g} attempts/s")
+    if args.bucket_shapes:
+        from paper_1004_0024_amd import tune
+        wd = make_workload("D")
+        gd, _ = tuned_graph(wd, reps=2)
+        out["bucket_shapes_side_by_side"] = tune.bucket_shapes_side_by_side(
+            pa.State(gd).init(wd.walker_seeds, wd.swap_seeds))
+        progress("bucket shapes side by side done")
     if not args.no_two_field:
         out["two_field"] = two_field_leg(max(2, args.steps // 2))
         out["two_field"]["over_one_field"] = out["two_field"]["value"] / value

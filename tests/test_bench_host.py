@@ -52,3 +52,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_side_by_side_shape_candidates():
+    """Threads per walker that the side-by-side refinement tries for a bucket: the
+    current count, the powers of two at and below S, and above 64 also S, ceil(S/2)
+    and their multiples of 64, within 8..1,024."""
+    from paper_1004_0024_amd.tune import _shape_candidates
+    assert _shape_candidates({"S": 392, "tpw": 512}) == [196, 256, 392, 448, 512]
+    assert _shape_candidates({"S": 288, "tpw": 256}) == [144, 192, 256, 288, 320, 512]
+    assert _shape_candidates({"S": 32, "tpw": 64}) == [16, 32, 64]
+    assert _shape_candidates({"S": 8, "tpw": 8}) == [8]
+    assert _shape_candidates({"S": 2048, "tpw": 1024}) == [1024]

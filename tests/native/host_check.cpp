@@ -1,8 +1,9 @@
 // Host-only checks of libising's planning code, built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_sanitizers.py (no GPU, no HIP
 // runtime call): validation and packing of systems of every workload shape and
-// of invalid ones, every launch shape of every bucket with its tiles and sweep
-// limit, and the threshold, acceptance and two-field rows.  Prints one line per
+// of invalid ones, the cell records of grid templates, every launch shape of
+// every bucket with its tiles and sweep limit, and the threshold, acceptance and
+// two-field rows.  Prints one line per
 // case and "host_check OK" at the end; any failed check exits non-zero.
 #include <math.h>
 #include <stdio.h>
@@ -99,6 +100,34 @@ static Sys random_graph(int N, int nE, int K, uint64_t seed, int maxdeg = 8) {
   return s;
 }
 
+// Cell records of a grid template against sums taken straight from the system
+// description: the constant part of each spin's boundary field, h - sum of J to
+// its neighbours outside the cell - 2 J_tau (when the records carry couplings by
+// direction), and minus the sum of J from each left spin to the right spins of
+// its cell.
+static void check_cell_records(const Sys &s, const SysHost &hs) {
+  if (hs.grid_L == 0) return;
+  std::vector<int> out(s.S, 0), in(s.S, 0);
+  for (size_t e = 0; e < s.u.size(); ++e) {
+    const int a = s.u[e], b = s.v[e];
+    if ((a >> 3) == (b >> 3)) {
+      in[(a & 4) ? b : a] += s.J[e];
+    } else {
+      out[a] += s.J[e];
+      out[b] += s.J[e];
+    }
+  }
+  for (int c = 0; c < s.S / 8; ++c) {
+    const uint32_t *rec = hs.cellrec.data() + (size_t)c * kCellRecWords;
+    for (int k = 0; k < 8; ++k) {
+      const int q = 8 * c + k;
+      const int hc = s.h[q] - out[q] - 2 * s.jt[q];
+      if (hs.cell_fast) CHECK((int)(int8_t)(uint8_t)(rec[32 + (k >> 2)] >> (8 * (k & 3))) == hc);
+      if (k < 4) CHECK((int)(int16_t)(uint16_t)(rec[34 + (k >> 1)] >> (16 * (k & 1))) == -in[q]);
+    }
+  }
+}
+
 // Plan a batch and try every launch shape of every bucket: tiles must cover
 // each walker of the bucket's systems exactly once.
 static void check_batch(const char *name, const std::vector<Sys> &systems) {
@@ -108,6 +137,7 @@ static void check_batch(const char *name, const std::vector<Sys> &systems) {
   CHECK(ising_graph_bytes(d.data(), (int32_t)d.size(), &bytes) == ISING_OK);
   std::vector<SysHost> hs;
   CHECK(build_all(d.data(), (int32_t)d.size(), hs) == ISING_OK);
+  for (size_t i = 0; i < systems.size(); ++i) check_cell_records(systems[i], hs[i]);
   GraphPlan g;
   CHECK(plan(hs, g) == ISING_OK);
   const int64_t default_limit = sweep_limit(g);

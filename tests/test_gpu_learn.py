@@ -78,3 +78,20 @@ def test_run_records_energies_and_ess():
     assert np.array_equal(e[-1], last)
     s = learn.ess_summary(g, e)
     assert 0 < s["coldest_total"] <= 2 * 160 and s["median_slot"] > 0
+
+
+def test_timed_cell_passes_leave_the_chain_unchanged():
+    """HIP events around each cell pass (learn.run's time_cells, which the benchmark
+    uses to time the kernels where the chains run them) give one positive time per
+    pass and the same chain as the untimed run."""
+    from paper_1004_0024_amd import learn
+    pa, g, st = _setup(n_sys=2, burn=50)
+    net = pa.Mlp(initial_params(3))
+    a, b = pa.State(g).copy_from(st), pa.State(g).copy_from(st)
+    ra = learn.run(a, 30, net, pass0=7)
+    rb = learn.run(b, 30, net, pass0=7, time_cells=True)
+    assert np.array_equal(ra["e"], rb["e"]) and np.array_equal(a.host("spins"), b.host("spins"))
+    assert "cell_pass_ms" not in ra
+    assert len(rb["cell_pass_ms"]) == 30 and min(rb["cell_pass_ms"]) > 0
+    rh = learn.run(pa.State(g).copy_from(st), 12, None, heatbath=True, cell_every=4, time_cells=True)
+    assert len(rh["cell_pass_ms"]) == 3 and min(rh["cell_pass_ms"]) > 0

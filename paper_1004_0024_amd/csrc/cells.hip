@@ -147,7 +147,7 @@ __device__ __forceinline__ int cell_delta_e(uint32_t nb, uint32_t cur, uint32_t 
 struct CellRow {
   bool valid;
   int r, ci;           // global walker, cell index (m*L + y)*L + x
-  int b[8];            // boundary fields
+  int b[8];            // boundary fields (an invalid lane reads a clamped row; its values go unused)
   int32_t jpack[4];    // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
   int njs[4];          // minus the sum over i of J between spin k < 4 and spin 4 + i
   float beta;

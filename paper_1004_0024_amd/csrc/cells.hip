@@ -151,7 +151,7 @@ struct CellRow {
   int32_t jpack[4];    // 2J of in-cell edges: spin k < 4 to spin 4 + i in byte i
   int njs[4];          // minus the sum over i of J between spin k < 4 and spin 4 + i
   float beta;
-  uint8_t *bytep;      // the cell's byte in the walker's spin words
+  int boff;            // byte offset of the cell's byte from the tile system's first spin word
   uint32_t cur;        // its current value (bit k = spin k is +1)
 };
 
@@ -160,6 +160,20 @@ struct TileSys {
   int w0, j0;  // walker and cell-list position of the tile's first row
   long long spin_word0;
 };
+
+// A buffer resource over memory from a wavefront-uniform base: loads through
+// it take a 32-bit byte offset per lane, so a lane's address needs no 64-bit
+// arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const void *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ uint32_t load_b32(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
+__device__ __forceinline__ uint4 load_b128(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+  return uint4{v[0], v[1], v[2], v[3]};
+}
 
 // Tables the kernels only read, through the scalar cache: with a uniform
 // address the loads are scalar and land in scalar registers.
@@ -223,32 +237,39 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
   c.valid = wk < u.K && j < u.count;
   const int wkc = c.valid ? wk : 0, jc = c.valid ? j : 0;
   c.r = c.valid ? u.walker0 + wk : -1;
-  const uint32_t pc = T.cells[u.cl0 + u.p0 + jc];
-  const int tof = St.temp_of[u.walker0 + wkc];
+  const uint32_t pc = load_b32(buffer_at(T.cells + u.cl0 + u.p0), 4 * jc);
+  const int tof = (int)load_b32(buffer_at(St.temp_of + u.walker0), 4 * wkc);
   const int m = (int)(pc >> 16), y = (int)((pc >> 8) & 0xffu), x = (int)(pc & 0xffu);
-  const int cc = y * u.L + x;
-  c.ci = m * u.LL + cc;
-  const uint32_t *sp = St.spins + u.spin_word0 + (size_t)wkc * u.WW;
-  const uint32_t *row = sp + m * u.RS;
+  // (the products below are of small counts: 24-bit multiplies, full rate)
+  const int cc = __mul24(y, u.L) + x;
+  c.ci = __mul24(m, u.LL) + cc;
+  // spin words from the system's first one: walker wkc, row m, word (cell >> 2)
+  const __amdgpu_buffer_rsrc_t spins = buffer_at(St.spins + u.spin_word0);
+  const int wofs = __mul24(wkc, u.WW), row = 4 * (wofs + __mul24(m, u.RS));
   const int mp = m == 0 ? u.M - 1 : m - 1, mn = m == u.M - 1 ? 0 : m + 1;
   const bool has_p = u.M > 1 && (m > 0 || u.ring), has_n = u.M > 1 && (m < u.M - 1 || u.ring);
   const int cu = y > 0 ? cc - u.L : cc, cd = y < u.L - 1 ? cc + u.L : cc;
   const int cl = x > 0 ? cc - 1 : cc, cr = x < u.L - 1 ? cc + 1 : cc;
-  const uint32_t wu = row[cu >> 2], wdn = row[cd >> 2], wl = row[cl >> 2], wr = row[cr >> 2], wo = row[cc >> 2];
-  const uint32_t wp = sp[mp * u.RS + (cc >> 2)], wn = sp[mn * u.RS + (cc >> 2)];
-  const uint4 *rec = (const uint4 *)(T.cellrec + (size_t)(u.cb0 + cc) * kCellRecWords);
-  const uint4 hq = rec[4], jq = rec[5];
+  const uint32_t wu = load_b32(spins, row + 4 * (cu >> 2)), wdn = load_b32(spins, row + 4 * (cd >> 2)),
+                 wl = load_b32(spins, row + 4 * (cl >> 2)), wr = load_b32(spins, row + 4 * (cr >> 2)),
+                 wo = load_b32(spins, row + 4 * (cc >> 2));
+  const uint32_t wp = load_b32(spins, 4 * (wofs + __mul24(mp, u.RS) + (cc >> 2))),
+                 wn = load_b32(spins, 4 * (wofs + __mul24(mn, u.RS) + (cc >> 2)));
+  // the cell's record: uint4 i at byte 16 i
+  const __amdgpu_buffer_rsrc_t recs = buffer_at(T.cellrec + (size_t)u.cb0 * kCellRecWords);
+  const int ro = __mul24(cc, 4 * kCellRecWords);
+  const uint4 hq = load_b128(recs, ro + 64), jq = load_b128(recs, ro + 80);
   auto cell_byte = [](uint32_t w, int q) { return (w >> ((q & 3) * 8)) & 0xffu; };
   const uint32_t nbytes = cell_byte(wu, cu) | (cell_byte(wdn, cd) << 8) | (cell_byte(wl, cl) << 16) |
                           (cell_byte(wr, cr) << 24);
   const uint32_t bp = has_p ? cell_byte(wp, cc) : 0u, bn = has_n ? cell_byte(wn, cc) : 0u;
-  const uint4 hx = rec[8];
+  const uint4 hx = load_b128(recs, ro + 128);
   if (u.fast) {
     // f_k = h''_k + sum_dir 2J bit + jtau_k U_k, with h''_k = h_k - sum_dir J - 2 jtau_k
     // from the record and U_k = 2 (bit k of the slice before, if any) + 2 (bit k
     // of the slice after, if any) + the number of missing tau neighbours, built
     // for all eight spins as bytes (0..4, no carries)
-    const uint4 d0 = rec[6], d1 = rec[7];
+    const uint4 d0 = load_b128(recs, ro + 96), d1 = load_b128(recs, ro + 112);
     const uint32_t dir[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
     const uint32_t pm = has_p ? bp : 0u, nm = has_n ? bn : 0u;
     const uint32_t miss = (has_p ? 0u : 0x01010101u) + (has_n ? 0u : 0x01010101u);
@@ -262,7 +283,8 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
       c.b[k] = __builtin_amdgcn_sdot4((int)((nbytes >> k) & 0x01010101u), (int)dir[k], h2, false) + jtau * uk;
     }
   } else {
-    const uint4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+    const uint4 r0 = load_b128(recs, ro), r1 = load_b128(recs, ro + 16), r2 = load_b128(recs, ro + 32),
+                r3 = load_b128(recs, ro + 48);
     const uint32_t ent[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
                               r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
 #pragma unroll
@@ -289,9 +311,10 @@ __device__ __forceinline__ void load_row(const DevTables &T, const DevState &St,
   c.njs[1] = (int)(int32_t)hx.z >> 16;
   c.njs[2] = (int)(int16_t)(hx.w & 0xffffu);
   c.njs[3] = (int)(int32_t)hx.w >> 16;
-  c.bytep = (uint8_t *)(St.spins + u.spin_word0 + (size_t)wkc * u.WW + m * u.RS + (cc >> 2)) + (cc & 3);
+  c.boff = row + cc;  // word cc >> 2 of the row, byte cc & 3
   c.cur = cell_byte(wo, cc);
-  c.beta = c.valid ? (float)T.beta[u.slot0 + tof] : 0.f;
+  const double beta = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buffer_at(T.beta + u.slot0), 8 * tof, 0, 0));
+  c.beta = c.valid ? (float)beta : 0.f;
 }
 
 // This wavefront's tiles: a contiguous run (the rows of one walker, then the
@@ -444,7 +467,8 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
   const TileRange tr = wave_tiles(rows_total / 64, kProposeWaves);
   for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     CellRow cr;
-    load_row(T, St, tile_system(T, tile, phase), l, cr);
+    const TileSys ts = tile_system(T, tile, phase);
+    load_row(T, St, ts, l, cr);
     const bool valid = cr.valid;
     const int *b = cr.b;
     const float beta = cr.beta;
@@ -555,7 +579,8 @@ __global__ void __launch_bounds__(64 * kProposeWaves) __attribute__((amdgpu_wave
       const float la = -beta * (float)dE + lratio;
       const float ua = (float)wd[8] * 0x1p-32f;
       accept = la >= 0.f || ua < __expf(la);
-      if (accept && nb != cur) *cr.bytep = (uint8_t)nb;
+      if (accept && nb != cur)
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)nb, buffer_at(St.spins + ts.spin_word0), cr.boff, 0, 0);
       if (!accept) dE = 0;
     }
     wave_fence();
@@ -589,7 +614,8 @@ __global__ void __launch_bounds__(256) cell_heatbath_kernel(DevTables T, DevStat
   const TileRange tr = wave_tiles(rows_total / 64, 4);
   for (int64_t tile = tr.begin; tile < tr.end; ++tile) {
     CellRow cr;
-    load_row(T, St, tile_system(T, tile, phase), l, cr);
+    const TileSys ts = tile_system(T, tile, phase);
+    load_row(T, St, ts, l, cr);
     int dE = 0;
     bool changed = false;
     if (cr.valid) {
@@ -651,7 +677,8 @@ __global__ void __launch_bounds__(256) cell_heatbath_kernel(DevTables T, DevStat
       }
       dE = cell_energy(nb, b, jin) - cell_energy(cr.cur, b, jin);
       changed = nb != cr.cur;
-      if (changed) *cr.bytep = (uint8_t)nb;
+      if (changed)
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)nb, buffer_at(St.spins + ts.spin_word0), cr.boff, 0, 0);
     }
     add_cell_moves(St, moves, cr.r, cr.valid, changed, dE, l);
   }
